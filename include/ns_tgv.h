@@ -1,0 +1,169 @@
+/*
+ * ns_tgv.h -- C ABI of the MI355X (gfx950) compressible Navier-Stokes
+ * residual + low-storage RK3 library.
+ *
+ * Method: Jammy, Jacobs, Lusher & Sandham, "Energy efficiency of finite
+ * difference algorithms on multicore CPUs, GPUs, and Intel Xeon Phi
+ * processors" (arXiv:1709.09713):
+ *   - governing equations: methodology section, mass / momentum / energy
+ *     equations with skew-symmetric convection and Laplacian-form viscous
+ *     terms, equation of state (pinprimitive) and (Tinprimitive);
+ *   - spatial discretisation: fourth-order central stencils (fd), (sd),
+ *     periodic in all three directions;
+ *   - temporal discretisation: three-stage low-storage Runge-Kutta (rk3_tvd)
+ *     arranged as in the generic-algorithm figure;
+ *   - test case: the Taylor-Green vortex of the results section.
+ *
+ * Conventions for every entry point:
+ *   - Fields are stored field-major: Q[v][k][j][i], v = 0..4 for
+ *     (rho, rho*u0, rho*u1, rho*u2, rho*E), i (x) fastest.  A "state" is
+ *     5*nx*ny*nz doubles in device memory.  Point (i,j,k) is at
+ *     (i*hx, j*hy, k*hz), h = length / n.
+ *   - Pointers named state, Q, R and work are DEVICE pointers owned by the
+ *     caller; the library keeps none of them after returning.  out_host is
+ *     a host pointer.
+ *   - stream is a hipStream_t (NULL = the default stream).  Calls are
+ *     stream-ordered and asynchronous, except diagnostics(), which waits for
+ *     its stream.
+ *   - Arguments are validated before anything is enqueued; a failed
+ *     validation returns an error and touches no memory.  HIP errors map to
+ *     NS_ERR_DEVICE.  No C++ exception crosses this boundary.  The library
+ *     allocates no device memory: scratch space is the caller's `work`
+ *     buffer of at least ns_workspace_bytes() bytes (256-byte aligned).
+ */
+#ifndef NS_TGV_H
+#define NS_TGV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NS_OK = 0,
+    NS_ERR_ARG = -1,         /* null pointer, bad enum, non-finite or out-of-range scalar */
+    NS_ERR_SHAPE = -2,       /* grid size outside [5, 2048] or too many points */
+    NS_ERR_WORKSPACE = -3,   /* work_bytes smaller than ns_workspace_bytes() or misaligned */
+    NS_ERR_DEVICE = -4,      /* a HIP call failed */
+    NS_ERR_NONFINITE = -5,   /* diagnostics found a NaN or infinity */
+    NS_ERR_UNSUPPORTED = -7  /* valid but not provided (stored class in FP32 storage) */
+} ns_status;
+
+/* The two algorithm classes compared in the algorithms section.
+ * NS_ALGO_STORED: every derivative is written to its own global array and
+ *   the residual is assembled from those arrays (the baseline algorithm,
+ *   BL).
+ * NS_ALGO_FUSED: no derivative array; derivatives are evaluated on the fly
+ *   from LDS-staged tiles and accumulated straight into the residual (the
+ *   minimal-storage class RA / SN / SN2). */
+typedef enum { NS_ALGO_STORED = 0, NS_ALGO_FUSED = 1 } ns_algo;
+
+/* NS_FP64: all storage and arithmetic in double.
+ * NS_FP32_STORE: the Runge-Kutta stage inputs are stored and differenced in
+ *   float, as deviations from the uniform reference state (rho = 1,
+ *   p = 1/(gamma M^2)); the RK accumulator, the state between steps and the
+ *   diagnostic reductions stay double.  Fused class only. */
+typedef enum { NS_FP64 = 0, NS_FP32_STORE = 1 } ns_precision;
+
+/* Grid and non-dimensional parameters (methodology section; results
+ * section: Re = 1600, Pr = 0.71, M = 0.1, gamma = 1.4, length = 2 pi).
+ * n[d] in [5, 2048] with nx*ny*nz < 2^31; length[d] > 0; gamma > 1;
+ * prandtl > 0; mach > 0; reynolds > 0 or +INFINITY (inviscid: 1/Re = 0 and
+ * no heat conduction). */
+typedef struct {
+    int32_t n[3];
+    double length[3];
+    double gamma;
+    double prandtl;
+    double reynolds;
+    double mach;
+} ns_params;
+
+/* Diagnostics of a state (the kinetic-energy / enstrophy quantities of the
+ * validation data set named in the results section):
+ *   mass = hx hy hz sum rho, momentum[i] = hx hy hz sum rho u_i,
+ *   energy = hx hy hz sum rho E, kinetic_energy = mean(rho |u|^2 / 2),
+ *   enstrophy = mean(rho |curl u|^2 / 2) with fourth-order first derivatives,
+ *   dissipation = 2 enstrophy / Re. */
+typedef struct {
+    double mass;
+    double momentum[3];
+    double energy;
+    double kinetic_energy;
+    double enstrophy;
+    double dissipation;
+} ns_diag;
+
+/* Human-readable name of a status code (static storage). */
+const char *ns_status_string(ns_status s);
+
+/* Bytes of one state (5 * nx*ny*nz doubles); 0 if params is invalid.
+ * The state is double for both precisions. */
+size_t ns_state_bytes(const ns_params *p);
+
+/* Bytes of caller-provided scratch that ns_residual / rk3_step /
+ * diagnostics need for this (algo, precision); 0 if the combination is
+ * invalid or unsupported.  Pure function. */
+size_t ns_workspace_bytes(const ns_params *p, ns_algo algo, ns_precision prec);
+
+/* Write the Taylor-Green vortex initial state of the results section into
+ * state (device, 5*N doubles):
+ *   u0 = sin(x/L) cos(y/L) cos(z/L), u1 = -cos(x/L) sin(y/L) cos(z/L),
+ *   u2 = 0, p = 1/(gamma M^2) + (cos(2x/L) + cos(2y/L))(2 + cos(2z/L))/16,
+ *   rho = gamma M^2 p (T = 1), rho E = p/(gamma-1) + rho |u|^2 / 2,
+ * with L = length[d] / (2 pi) per direction. */
+ns_status tgv_init(const ns_params *p, double *state, void *stream);
+
+/* One evaluation of the residual R(Q) (the right-hand sides of the mass,
+ * momentum and energy equations, discretised with (fd)/(sd) and periodic
+ * boundaries), FP64, with the chosen algorithm class.  Q and R are device
+ * arrays of 5*N doubles and must not overlap; Q is not modified.  work
+ * needs ns_workspace_bytes(p, algo, NS_FP64) bytes. */
+ns_status ns_residual(const ns_params *p, ns_algo algo, const double *Q,
+                      double *R, void *work, size_t work_bytes, void *stream);
+
+/* Advance state (device, 5*N doubles) in place by nsteps full steps of the
+ * three-stage low-storage Runge-Kutta scheme: per step, with Q_acc = Q^n,
+ * for k = 1..3: R = R(Q); Q = Q_acc + a_k dt R; Q_acc += b_k dt R, with
+ * a = (2/3, 5/12, 3/5), b = (1/4, 3/20, 3/5).  dt > 0 and finite;
+ * nsteps >= 0.  If diag_dev is not NULL it is a device array of nsteps
+ * ns_diag records: record s receives the diagnostics of the state at the
+ * start of step s (computed inside the first stage).  work needs
+ * ns_workspace_bytes(p, algo, prec) bytes.  algo = NS_ALGO_STORED requires
+ * prec = NS_FP64 (else NS_ERR_UNSUPPORTED). */
+ns_status rk3_step(const ns_params *p, ns_algo algo, ns_precision prec,
+                   double dt, int32_t nsteps, double *state, void *work,
+                   size_t work_bytes, ns_diag *diag_dev, void *stream);
+
+/* Diagnostics of state (device, 5*N doubles) into *out_host, in FP64 with a
+ * fixed reduction order (bitwise reproducible).  Waits for stream.  work
+ * needs ns_workspace_bytes(p, NS_ALGO_FUSED, NS_FP64) bytes.  Returns
+ * NS_ERR_NONFINITE (after filling *out_host) if any value is not finite. */
+ns_status diagnostics(const ns_params *p, const double *state,
+                      ns_diag *out_host, void *work, size_t work_bytes,
+                      void *stream);
+
+/* Launch shape of the fused kernel, process-wide.  tile selects the
+ * (x, y) column tile of one block: 0 = 32x8, 1 = 16x16, 2 = 64x4,
+ * 3 = 32x16 (threads = product, one z column each); zchunk is the number of
+ * z planes one block marches through (>= 4; 0 = automatic).  tile = -1
+ * restores the automatic choice.  For a given tile, residuals and states
+ * are bitwise independent of zchunk; different tiles are separate compiled
+ * instances and may differ at the rounding level (the compiler can contract
+ * a multiply-add differently); per-step diagnostics also differ in the
+ * order of their sums.
+ * Returns NS_ERR_ARG for out-of-range values.  Not thread-safe with
+ * concurrent launches that expect a different shape. */
+ns_status ns_set_fused_config(int32_t tile, int32_t zchunk);
+
+/* The (tile, zchunk) the fused kernel would use for p right now. */
+ns_status ns_get_fused_config(const ns_params *p, int32_t *tile,
+                              int32_t *zchunk);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NS_TGV_H */

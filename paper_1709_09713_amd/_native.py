@@ -1,0 +1,197 @@
+"""ctypes binding of ``libns_tgv.so`` (the C ABI declared in
+``include/ns_tgv.h``).  Argument marshalling only: every step of the
+residual / RK3 path runs in the HIP kernels of the library.
+
+Device buffers are passed as raw device addresses (``int``) or as torch CUDA
+tensors (their ``data_ptr()``); PyTorch is used for device memory and streams
+only.  There is no CPU fallback: if the library is missing, loading fails
+with an error that says how to build it.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libns_tgv.so")
+
+NS_OK = 0
+NS_ERR_ARG = -1
+NS_ERR_SHAPE = -2
+NS_ERR_WORKSPACE = -3
+NS_ERR_DEVICE = -4
+NS_ERR_NONFINITE = -5
+NS_ERR_UNSUPPORTED = -7
+
+NS_ALGO_STORED = 0
+NS_ALGO_FUSED = 1
+NS_FP64 = 0
+NS_FP32_STORE = 1
+
+ALGOS = {"stored": NS_ALGO_STORED, "fused": NS_ALGO_FUSED}
+PRECS = {"fp64": NS_FP64, "fp32": NS_FP32_STORE}
+
+TILES = {0: (32, 8), 1: (16, 16), 2: (64, 4), 3: (32, 16)}
+
+
+class ns_params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("length", ctypes.c_double * 3),
+                ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double),
+                ("reynolds", ctypes.c_double), ("mach", ctypes.c_double)]
+
+
+class ns_diag(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3),
+                ("energy", ctypes.c_double), ("kinetic_energy", ctypes.c_double),
+                ("enstrophy", ctypes.c_double), ("dissipation", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"mass": self.mass, "momentum_x": self.momentum[0],
+                "momentum_y": self.momentum[1], "momentum_z": self.momentum[2],
+                "energy": self.energy, "kinetic_energy": self.kinetic_energy,
+                "enstrophy": self.enstrophy, "dissipation": self.dissipation}
+
+
+DIAG_NAMES = ("mass", "momentum_x", "momentum_y", "momentum_z", "energy",
+              "kinetic_energy", "enstrophy", "dissipation")
+
+# Exported C symbols, in header order.
+EXPORTS = ("ns_status_string", "ns_state_bytes", "ns_workspace_bytes",
+           "tgv_init", "ns_residual", "rk3_step", "diagnostics",
+           "ns_set_fused_config", "ns_get_fused_config")
+
+
+class NativeError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (ctypes.CDLL); raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -c 'import __graft_entry__ as g; g.build()'` "
+                "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(ns_params)
+        vp, sz, i32, d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double
+        L.ns_status_string.restype = ctypes.c_char_p
+        L.ns_status_string.argtypes = [ctypes.c_int]
+        L.ns_state_bytes.restype = sz
+        L.ns_state_bytes.argtypes = [P]
+        L.ns_workspace_bytes.restype = sz
+        L.ns_workspace_bytes.argtypes = [P, ctypes.c_int, ctypes.c_int]
+        L.tgv_init.restype = ctypes.c_int
+        L.tgv_init.argtypes = [P, vp, vp]
+        L.ns_residual.restype = ctypes.c_int
+        L.ns_residual.argtypes = [P, ctypes.c_int, vp, vp, vp, sz, vp]
+        L.rk3_step.restype = ctypes.c_int
+        L.rk3_step.argtypes = [P, ctypes.c_int, ctypes.c_int, d, i32, vp, vp, sz, vp, vp]
+        L.diagnostics.restype = ctypes.c_int
+        L.diagnostics.argtypes = [P, vp, ctypes.POINTER(ns_diag), vp, sz, vp]
+        L.ns_set_fused_config.restype = ctypes.c_int
+        L.ns_set_fused_config.argtypes = [i32, i32]
+        L.ns_get_fused_config.restype = ctypes.c_int
+        L.ns_get_fused_config.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().ns_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str):
+    if status != NS_OK:
+        raise NativeError(status, where)
+
+
+def make_params(n, length=None, gamma=1.4, prandtl=0.71, reynolds=1600.0,
+                mach=0.1) -> ns_params:
+    if isinstance(n, int):
+        n = (n, n, n)
+    if length is None:
+        length = (2 * math.pi,) * 3
+    p = ns_params()
+    p.n[:] = [int(x) for x in n]
+    p.length[:] = [float(x) for x in length]
+    p.gamma, p.prandtl, p.reynolds, p.mach = (float(gamma), float(prandtl),
+                                              float(reynolds), float(mach))
+    return p
+
+
+def _ptr(x) -> int | None:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def ns_state_bytes(p: ns_params) -> int:
+    return lib().ns_state_bytes(ctypes.byref(p))
+
+
+def ns_workspace_bytes(p: ns_params, algo: int, prec: int = NS_FP64) -> int:
+    return lib().ns_workspace_bytes(ctypes.byref(p), int(algo), int(prec))
+
+
+def tgv_init(p: ns_params, state, stream=None):
+    _check(lib().tgv_init(ctypes.byref(p), _ptr(state), _stream(stream)), "tgv_init")
+
+
+def ns_residual(p: ns_params, algo: int, Q, R, work=None, work_bytes: int = 0,
+                stream=None):
+    if work is not None and work_bytes == 0 and not isinstance(work, int):
+        work_bytes = work.numel() * work.element_size()
+    _check(lib().ns_residual(ctypes.byref(p), int(algo), _ptr(Q), _ptr(R), _ptr(work),
+                             work_bytes, _stream(stream)), "ns_residual")
+
+
+def rk3_step(p: ns_params, algo: int, prec: int, dt: float, nsteps: int, state,
+             work, work_bytes: int = 0, diag_dev=None, stream=None):
+    if work_bytes == 0 and work is not None and not isinstance(work, int):
+        work_bytes = work.numel() * work.element_size()
+    _check(lib().rk3_step(ctypes.byref(p), int(algo), int(prec), float(dt), int(nsteps),
+                          _ptr(state), _ptr(work), work_bytes, _ptr(diag_dev),
+                          _stream(stream)), "rk3_step")
+
+
+def diagnostics(p: ns_params, state, work, work_bytes: int = 0, stream=None) -> dict:
+    if work_bytes == 0 and work is not None and not isinstance(work, int):
+        work_bytes = work.numel() * work.element_size()
+    out = ns_diag()
+    st = lib().diagnostics(ctypes.byref(p), _ptr(state), ctypes.byref(out), _ptr(work),
+                           work_bytes, _stream(stream))
+    if st not in (NS_OK, NS_ERR_NONFINITE):
+        _check(st, "diagnostics")
+    d = out.as_dict()
+    d["status"] = st
+    return d
+
+
+def ns_set_fused_config(tile: int, zchunk: int = 0):
+    _check(lib().ns_set_fused_config(int(tile), int(zchunk)), "ns_set_fused_config")
+
+
+def ns_get_fused_config(p: ns_params):
+    t, z = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().ns_get_fused_config(ctypes.byref(p), ctypes.byref(t), ctypes.byref(z)),
+           "ns_get_fused_config")
+    return t.value, z.value

@@ -1,0 +1,348 @@
+// ns_api.hip -- the C ABI (include/ns_tgv.h): argument validation,
+// workspace layout and the per-step launch sequence of both algorithm
+// classes.  Every call validates first and enqueues nothing on failure.
+#include <atomic>
+#include <cmath>
+#include <cstring>
+
+#include "ns_common.hpp"
+#include "ns_kernels.hpp"
+
+namespace ns {
+
+Consts make_consts(const ns_params *p)
+{
+    Consts c;
+    c.nx = p->n[0];
+    c.ny = p->n[1];
+    c.nz = p->n[2];
+    c.nxy = c.nx * c.ny;
+    c.N = (int64_t)c.nxy * c.nz;
+    double h[3];
+    for (int d = 0; d < 3; ++d) {
+        h[d] = p->length[d] / p->n[d];
+        c.c1[d] = 1.0 / (12.0 * h[d]);
+        c.c2[d] = 1.0 / (12.0 * h[d] * h[d]);
+    }
+    c.gm1 = p->gamma - 1.0;
+    c.gM2 = p->gamma * p->mach * p->mach;
+    c.inv_re = 1.0 / p->reynolds;   // 0 for +INFINITY
+    c.kappa = 1.0 / (c.gm1 * p->mach * p->mach * p->prandtl * p->reynolds);
+    c.rho_ref = 1.0;
+    c.p_ref = 1.0 / c.gM2;
+    c.rhoE_ref = c.p_ref / c.gm1;
+    c.H_ref = c.rhoE_ref + c.p_ref;
+    c.vol = h[0] * h[1] * h[2];
+    c.inv_npts = 1.0 / (double)c.N;
+    return c;
+}
+
+// RK3 coefficients of the two-register low-storage scheme.
+static const double kRkA[3] = {2.0 / 3.0, 5.0 / 12.0, 3.0 / 5.0};
+static const double kRkB[3] = {1.0 / 4.0, 3.0 / 20.0, 3.0 / 5.0};
+
+constexpr int kMinZChunk = 4;
+static std::atomic<int> g_tile{-1};
+static std::atomic<int> g_zchunk{0};
+
+static void choose_config(const Consts &c, int *tile, int *zchunk)
+{
+    int t = g_tile.load();
+    int z = g_zchunk.load();
+    if (t < 0 || t >= TILE_COUNT) t = TILE_32x8;
+    if (z <= 0) {
+        int bx, by;
+        tile_dims(t, &bx, &by);
+        const int64_t xy = (int64_t)((c.nx + bx - 1) / bx) * ((c.ny + by - 1) / by);
+        const int64_t want = 2048;
+        const int64_t nzc = (want + xy - 1) / xy;
+        z = (int)((c.nz + nzc - 1) / nzc);
+        if (z < 16) z = 16;
+    }
+    if (z < kMinZChunk) z = kMinZChunk;
+    if (z > c.nz) z = c.nz;
+    *tile = t;
+    *zchunk = z;
+}
+
+static int64_t max_partial_blocks(const Consts &c)
+{
+    int64_t m = diag_num_blocks(c);
+    for (int t = 0; t < TILE_COUNT; ++t) {
+        const int64_t b = fused_num_blocks(c, t, kMinZChunk);
+        if (b > m) m = b;
+    }
+    return m;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t partial, rec, acc, b1, b2, R, stored, total;
+};
+
+// Scratch layout.  The diagnostic partials and one ns_diag record come
+// first, so every workspace size returned by ns_workspace_bytes also serves
+// diagnostics().
+static Layout layout(const Consts &c, ns_algo algo, ns_precision prec)
+{
+    Layout L;
+    size_t off = 0;
+    const size_t n5 = 5 * (size_t)c.N;
+    L.partial = off;
+    off = align256(off + (size_t)max_partial_blocks(c) * kDiag * sizeof(double));
+    L.rec = off;
+    off = align256(off + sizeof(ns_diag));
+    const size_t stage_elt = (prec == NS_FP64) ? sizeof(double) : sizeof(float);
+    L.acc = off;
+    off = align256(off + n5 * sizeof(double));
+    L.b1 = off;
+    off = align256(off + n5 * stage_elt);
+    L.b2 = off;
+    off = align256(off + n5 * stage_elt);
+    L.R = L.stored = 0;
+    if (algo == NS_ALGO_STORED) {
+        L.R = off;
+        off = align256(off + n5 * sizeof(double));
+        L.stored = off;
+        off = align256(off + stored_workspace_doubles(c) * sizeof(double));
+    }
+    L.total = off;
+    return L;
+}
+
+static size_t diag_bytes(const Consts &c)
+{
+    return align256((size_t)max_partial_blocks(c) * kDiag * sizeof(double)) + align256(sizeof(ns_diag));
+}
+
+static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+static ns_status check_params(const ns_params *p)
+{
+    if (!p) return NS_ERR_ARG;
+    int64_t n = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (p->n[d] < 5 || p->n[d] > 2048) return NS_ERR_SHAPE;
+        n *= p->n[d];
+        if (!finite_pos(p->length[d])) return NS_ERR_ARG;
+    }
+    if (n >= ((int64_t)1 << 31)) return NS_ERR_SHAPE;
+    if (!std::isfinite(p->gamma) || !(p->gamma > 1.0)) return NS_ERR_ARG;
+    if (!finite_pos(p->prandtl) || !finite_pos(p->mach)) return NS_ERR_ARG;
+    if (std::isnan(p->reynolds) || !(p->reynolds > 0.0)) return NS_ERR_ARG;
+    return NS_OK;
+}
+
+static bool valid_algo(int a) { return a == NS_ALGO_STORED || a == NS_ALGO_FUSED; }
+static bool valid_prec(int q) { return q == NS_FP64 || q == NS_FP32_STORE; }
+
+static ns_status check_work(const void *work, size_t have, size_t need)
+{
+    if (need > 0 && !work) return NS_ERR_ARG;
+    if (have < need) return NS_ERR_WORKSPACE;
+    if (((uintptr_t)work & 255) != 0) return NS_ERR_WORKSPACE;
+    return NS_OK;
+}
+
+template <typename T>
+static T *at(void *work, size_t off)
+{
+    return (T *)((char *)work + off);
+}
+
+}  // namespace ns
+
+using namespace ns;
+
+extern "C" {
+
+const char *ns_status_string(ns_status s)
+{
+    switch (s) {
+    case NS_OK: return "NS_OK";
+    case NS_ERR_ARG: return "NS_ERR_ARG: invalid argument";
+    case NS_ERR_SHAPE: return "NS_ERR_SHAPE: grid size out of range";
+    case NS_ERR_WORKSPACE: return "NS_ERR_WORKSPACE: workspace too small or misaligned";
+    case NS_ERR_DEVICE: return "NS_ERR_DEVICE: HIP error";
+    case NS_ERR_NONFINITE: return "NS_ERR_NONFINITE: non-finite diagnostics";
+    case NS_ERR_UNSUPPORTED: return "NS_ERR_UNSUPPORTED: combination not provided";
+    }
+    return "unknown ns_status";
+}
+
+size_t ns_state_bytes(const ns_params *p)
+{
+    if (check_params(p) != NS_OK) return 0;
+    return 5 * (size_t)p->n[0] * p->n[1] * p->n[2] * sizeof(double);
+}
+
+size_t ns_workspace_bytes(const ns_params *p, ns_algo algo, ns_precision prec)
+{
+    if (check_params(p) != NS_OK || !valid_algo(algo) || !valid_prec(prec)) return 0;
+    if (algo == NS_ALGO_STORED && prec != NS_FP64) return 0;
+    return layout(make_consts(p), algo, prec).total;
+}
+
+ns_status ns_set_fused_config(int32_t tile, int32_t zchunk)
+{
+    if (tile < -1 || tile >= TILE_COUNT || zchunk < 0) return NS_ERR_ARG;
+    if (zchunk > 0 && zchunk < kMinZChunk) return NS_ERR_ARG;
+    g_tile.store(tile);
+    g_zchunk.store(zchunk);
+    return NS_OK;
+}
+
+ns_status ns_get_fused_config(const ns_params *p, int32_t *tile, int32_t *zchunk)
+{
+    ns_status st = check_params(p);
+    if (st != NS_OK) return st;
+    if (!tile || !zchunk) return NS_ERR_ARG;
+    int t, z;
+    choose_config(make_consts(p), &t, &z);
+    *tile = t;
+    *zchunk = z;
+    return NS_OK;
+}
+
+ns_status tgv_init(const ns_params *p, double *state, void *stream)
+{
+    ns_status st = check_params(p);
+    if (st != NS_OK) return st;
+    if (!state) return NS_ERR_ARG;
+    const Consts c = make_consts(p);
+    NS_HIP_OK(launch_tgv_init(c, p, state, (hipStream_t)stream));
+    return NS_OK;
+}
+
+ns_status ns_residual(const ns_params *p, ns_algo algo, const double *Q, double *R, void *work,
+                      size_t work_bytes, void *stream)
+{
+    ns_status st = check_params(p);
+    if (st != NS_OK) return st;
+    if (!valid_algo(algo) || !Q || !R) return NS_ERR_ARG;
+    const Consts c = make_consts(p);
+    const size_t n5b = 5 * (size_t)c.N * sizeof(double);
+    if ((const char *)Q < (const char *)R + n5b && (const char *)R < (const char *)Q + n5b)
+        return NS_ERR_ARG;   // overlap
+    hipStream_t s = (hipStream_t)stream;
+    if (algo == NS_ALGO_FUSED) {
+        int tile, zc;
+        choose_config(c, &tile, &zc);
+        StageArgs a = {};
+        a.qin = Q;
+        a.rout = R;
+        a.mode = 0;
+        a.zchunk = zc;
+        NS_HIP_OK(launch_fused_stage(c, a, NS_FP64, tile, s));
+        return NS_OK;
+    }
+    const Layout L = layout(c, algo, NS_FP64);
+    st = check_work(work, work_bytes, L.total);
+    if (st != NS_OK) return st;
+    NS_HIP_OK(stored_residual(c, Q, R, at<double>(work, L.stored), s));
+    return NS_OK;
+}
+
+ns_status rk3_step(const ns_params *p, ns_algo algo, ns_precision prec, double dt, int32_t nsteps,
+                   double *state, void *work, size_t work_bytes, ns_diag *diag_dev, void *stream)
+{
+    ns_status st = check_params(p);
+    if (st != NS_OK) return st;
+    if (!valid_algo(algo) || !valid_prec(prec) || !state) return NS_ERR_ARG;
+    if (!std::isfinite(dt) || !(dt > 0.0) || nsteps < 0) return NS_ERR_ARG;
+    if (algo == NS_ALGO_STORED && prec != NS_FP64) return NS_ERR_UNSUPPORTED;
+    const Consts c = make_consts(p);
+    const Layout L = layout(c, algo, prec);
+    st = check_work(work, work_bytes, L.total);
+    if (st != NS_OK) return st;
+    if (nsteps == 0) return NS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    double *partial = at<double>(work, L.partial);
+    double *acc = at<double>(work, L.acc);
+    void *b1 = at<void>(work, L.b1);
+    void *b2 = at<void>(work, L.b2);
+
+    if (algo == NS_ALGO_FUSED) {
+        int tile, zc;
+        choose_config(c, &tile, &zc);
+        const int64_t nblk = fused_num_blocks(c, tile, zc);
+        for (int32_t step = 0; step < nsteps; ++step) {
+            StageArgs a = {};
+            a.zchunk = zc;
+            // stage 1: Q^n -> b1 (next stage input), acc
+            a.qin = state;
+            a.qout = b1;
+            a.acc_out = acc;
+            a.a_dt = kRkA[0] * dt;
+            a.b_dt = kRkB[0] * dt;
+            a.mode = 1;
+            a.diag_partial = diag_dev ? partial : nullptr;
+            NS_HIP_OK(launch_fused_stage(c, a, prec, tile, s));
+            if (diag_dev) NS_HIP_OK(launch_diag_finalize(c, partial, nblk, diag_dev + step, s));
+            // stage 2: b1 -> b2, acc in place
+            a.qin = b1;
+            a.acc_in = acc;
+            a.acc_out = acc;
+            a.qout = b2;
+            a.a_dt = kRkA[1] * dt;
+            a.b_dt = kRkB[1] * dt;
+            a.mode = 2;
+            a.diag_partial = nullptr;
+            NS_HIP_OK(launch_fused_stage(c, a, prec, tile, s));
+            // stage 3: b2 -> Q^{n+1} in state
+            a.qin = b2;
+            a.acc_in = acc;
+            a.acc_out = nullptr;
+            a.qout = state;
+            a.a_dt = kRkA[2] * dt;
+            a.b_dt = 0.0;
+            a.mode = 3;
+            NS_HIP_OK(launch_fused_stage(c, a, prec, tile, s));
+        }
+        return NS_OK;
+    }
+
+    // stored-derivative class
+    double *R = at<double>(work, L.R);
+    double *wk = at<double>(work, L.stored);
+    double *q1 = (double *)b1, *q2 = (double *)b2;
+    for (int32_t step = 0; step < nsteps; ++step) {
+        if (diag_dev) {
+            NS_HIP_OK(launch_diag_partials(c, state, partial, s));
+            NS_HIP_OK(launch_diag_finalize(c, partial, diag_num_blocks(c), diag_dev + step, s));
+        }
+        NS_HIP_OK(stored_residual(c, state, R, wk, s));
+        NS_HIP_OK(launch_rk_update(c, R, state, acc, q1, kRkA[0] * dt, kRkB[0] * dt, s));
+        NS_HIP_OK(stored_residual(c, q1, R, wk, s));
+        NS_HIP_OK(launch_rk_update(c, R, acc, acc, q2, kRkA[1] * dt, kRkB[1] * dt, s));
+        NS_HIP_OK(stored_residual(c, q2, R, wk, s));
+        NS_HIP_OK(launch_rk_update(c, R, acc, nullptr, state, kRkA[2] * dt, 0.0, s));
+    }
+    return NS_OK;
+}
+
+ns_status diagnostics(const ns_params *p, const double *state, ns_diag *out_host, void *work,
+                      size_t work_bytes, void *stream)
+{
+    ns_status st = check_params(p);
+    if (st != NS_OK) return st;
+    if (!state || !out_host) return NS_ERR_ARG;
+    const Consts c = make_consts(p);
+    const Layout L = layout(c, NS_ALGO_FUSED, NS_FP64);
+    st = check_work(work, work_bytes, diag_bytes(c));
+    if (st != NS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    double *partial = at<double>(work, L.partial);
+    ns_diag *rec = at<ns_diag>(work, L.rec);
+    NS_HIP_OK(launch_diag_partials(c, state, partial, s));
+    NS_HIP_OK(launch_diag_finalize(c, partial, diag_num_blocks(c), rec, s));
+    NS_HIP_OK(hipMemcpyAsync(out_host, rec, sizeof(ns_diag), hipMemcpyDeviceToHost, s));
+    NS_HIP_OK(hipStreamSynchronize(s));
+    const double *v = (const double *)out_host;
+    for (int k = 0; k < 8; ++k)
+        if (!std::isfinite(v[k])) return NS_ERR_NONFINITE;
+    return NS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// ns_common.hpp -- shared device-side definitions of the HIP library.
+//
+// Grid constants are folded on the host once per call (the paper evaluates
+// rationals and inverses of constants up front so that the loops contain no
+// divisions: end of the algorithms section).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ns_tgv.h"
+
+namespace ns {
+
+// Conserved-variable slots in a state, field-major.
+enum { F_RHO = 0, F_M0 = 1, F_M1 = 2, F_M2 = 3, F_E = 4 };
+
+// Number of doubles in one diagnostics record / per-block partial.
+constexpr int kDiag = 8;
+
+struct Consts {
+    int nx, ny, nz;
+    int nxy;
+    int64_t N;          // points per field
+    double c1[3];       // 1 / (12 h_d): scale of the unscaled first-derivative stencil
+    double c2[3];       // 1 / (12 h_d^2): scale of the unscaled second-derivative stencil
+    double gm1;         // gamma - 1
+    double gM2;         // gamma M^2
+    double inv_re;      // 1 / Re (0 when inviscid)
+    double kappa;       // 1 / ((gamma - 1) M^2 Pr Re)
+    // Uniform reference state used by the FP32 storage format:
+    // rho_ref = 1, p_ref = 1/(gamma M^2), rhoE_ref = p_ref/(gamma - 1).
+    double rho_ref, p_ref, rhoE_ref, H_ref;   // H_ref = rhoE_ref + p_ref
+    double vol;         // hx hy hz
+    double inv_npts;    // 1 / N
+};
+
+Consts make_consts(const ns_params *p);
+
+__host__ __device__ inline int wrap1(int i, int n)
+{
+    // single wrap: valid for -n <= i < 2n
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+// Unscaled fourth-order first-derivative stencil (equation fd, times 12h):
+//   (f[-2] - f[+2]) + 8 (f[+1] - f[-1]).
+template <typename T>
+__device__ __forceinline__ T d1u(T fm2, T fm1, T fp1, T fp2)
+{
+    return (fm2 - fp2) + T(8) * (fp1 - fm1);
+}
+
+// Unscaled fourth-order second-derivative stencil (equation sd, times 12h^2):
+//   16 (f[-1] + f[+1]) - (f[-2] + f[+2]) - 30 f[0].
+template <typename T>
+__device__ __forceinline__ T d2u(T fm2, T fm1, T f0, T fp1, T fp2)
+{
+    return T(16) * (fm1 + fp1) - (fm2 + fp2) - T(30) * f0;
+}
+
+}  // namespace ns
+
+#define NS_HIP_OK(expr)                                       \
+    do {                                                      \
+        if ((expr) != hipSuccess) return NS_ERR_DEVICE;       \
+    } while (0)

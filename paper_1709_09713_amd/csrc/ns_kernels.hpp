@@ -1,0 +1,49 @@
+// ns_kernels.hpp -- launch interfaces of the device kernels (host side).
+#pragma once
+
+#include "ns_common.hpp"
+
+namespace ns {
+
+// Column-tile shapes of the fused kernel (threads = BX * BY, one z column
+// each).  Chosen per problem by the autotuner or by the default rule.
+enum { TILE_32x8 = 0, TILE_16x16 = 1, TILE_64x4 = 2, TILE_32x16 = 3, TILE_COUNT = 4 };
+
+// One fused launch: residual only (mode 0) or RK stage 1..3.
+struct StageArgs {
+    const void *qin;        // stencil input state (double, or float deviations)
+    const double *acc_in;   // RK accumulator in (stages 2, 3)
+    double *acc_out;        // RK accumulator out (stages 1, 2)
+    void *qout;             // stage output (stages 1, 2: next stage input; 3: state)
+    double *rout;           // residual output (mode 0)
+    double a_dt, b_dt;      // a_k dt and b_k dt
+    int mode;               // 0 = residual, 1..3 = RK stage
+    int zchunk;             // planes per block along z
+    double *diag_partial;   // per-block diagnostic partial sums, or nullptr
+};
+
+void tile_dims(int tile, int *bx, int *by);
+int64_t fused_num_blocks(const Consts &c, int tile, int zchunk);
+hipError_t launch_fused_stage(const Consts &c, const StageArgs &s, ns_precision prec,
+                              int tile, hipStream_t st);
+
+// Diagnostics: per-block partial sums of a state, then a one-block fixed-order
+// final reduction into an ns_diag record.
+int64_t diag_num_blocks(const Consts &c);
+hipError_t launch_diag_partials(const Consts &c, const double *state, double *partial,
+                                hipStream_t st);
+hipError_t launch_diag_finalize(const Consts &c, const double *partial, int64_t nblocks,
+                                ns_diag *out, hipStream_t st);
+
+// Taylor-Green initial state.
+hipError_t launch_tgv_init(const Consts &c, const ns_params *p, double *state, hipStream_t st);
+
+// Stored-derivative (baseline) class.
+size_t stored_workspace_doubles(const Consts &c);
+hipError_t stored_residual(const Consts &c, const double *Q, double *R, double *work,
+                           hipStream_t st);
+hipError_t launch_rk_update(const Consts &c, const double *R, const double *acc_in,
+                            double *acc_out, double *qout, double a_dt, double b_dt,
+                            hipStream_t st);
+
+}  // namespace ns

@@ -1,0 +1,148 @@
+"""The C-ABI library loads, exports every symbol include/ns_tgv.h declares,
+and validates its arguments before touching the device (CPU only: none of
+these calls reaches a kernel)."""
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1709_09713_amd as ns
+from paper_1709_09713_amd import _native as nat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ns_tgv.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+
+
+def test_header_declares_the_boundary():
+    fns = header_functions()
+    for name in ("tgv_init", "ns_residual", "rk3_step", "diagnostics",
+                 "ns_state_bytes", "ns_workspace_bytes", "ns_status_string"):
+        assert name in fns
+    assert tuple(fns) == nat.EXPORTS
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.check_output(["nm", "-D", "--defined-only", nat.LIB_PATH]).decode()
+    syms = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in header_functions():
+        assert name in syms, name
+        assert getattr(ns.lib(), name) is not None
+
+
+def test_status_strings():
+    for code in (0, -1, -2, -3, -4, -5, -7):
+        assert ns.status_string(code).startswith("NS_")
+
+
+def test_sizes():
+    p = ns.make_params(16)
+    assert ns.ns_state_bytes(p) == 5 * 16 ** 3 * 8
+    wf = ns.ns_workspace_bytes(p, ns.NS_ALGO_FUSED, ns.NS_FP64)
+    w32 = ns.ns_workspace_bytes(p, ns.NS_ALGO_FUSED, ns.NS_FP32_STORE)
+    ws = ns.ns_workspace_bytes(p, ns.NS_ALGO_STORED, ns.NS_FP64)
+    assert wf >= 3 * 5 * 16 ** 3 * 8          # accumulator + two stage buffers
+    assert 5 * 16 ** 3 * 16 <= w32 < wf        # float stage buffers
+    assert ws >= wf + 85 * 16 ** 3 * 8         # residual + 80 work arrays
+    assert ns.ns_workspace_bytes(p, ns.NS_ALGO_STORED, ns.NS_FP32_STORE) == 0
+    assert ns.ns_workspace_bytes(p, 7, ns.NS_FP64) == 0
+    p2 = ns.make_params((5, 6, 7))
+    assert ns.ns_state_bytes(p2) == 5 * 5 * 6 * 7 * 8
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("n", (4, 16, 16), ns.NS_ERR_SHAPE),
+    ("n", (16, 2049, 16), ns.NS_ERR_SHAPE),
+    ("n", (2048, 2048, 2048), ns.NS_ERR_SHAPE),
+    ("gamma", 1.0, ns.NS_ERR_ARG),
+    ("gamma", float("nan"), ns.NS_ERR_ARG),
+    ("mach", 0.0, ns.NS_ERR_ARG),
+    ("prandtl", -1.0, ns.NS_ERR_ARG),
+    ("reynolds", float("nan"), ns.NS_ERR_ARG),
+    ("reynolds", -5.0, ns.NS_ERR_ARG),
+    ("length", (0.0, 1.0, 1.0), ns.NS_ERR_ARG),
+])
+def test_bad_params_rejected_before_any_launch(field, value, code):
+    kw = dict(n=16)
+    if field == "n":
+        kw["n"] = value
+    elif field == "length":
+        kw["length"] = value
+    else:
+        kw[field] = value
+    p = ns.make_params(**kw)
+    assert ns.ns_state_bytes(p) == 0
+    # a bogus but non-null device pointer: validation must fail first
+    with pytest.raises(ns.NativeError) as e:
+        ns.tgv_init(p, 0x1000)
+    assert e.value.status == code
+    with pytest.raises(ns.NativeError) as e:
+        ns.rk3_step(p, ns.NS_ALGO_FUSED, ns.NS_FP64, 1e-3, 1, 0x1000, 0x1000, 1 << 40)
+    assert e.value.status == code
+
+
+def test_inviscid_is_valid():
+    p = ns.make_params(16, reynolds=math.inf)
+    assert ns.ns_state_bytes(p) > 0
+
+
+def test_rk3_argument_checks():
+    p = ns.make_params(16)
+    wb = ns.ns_workspace_bytes(p, ns.NS_ALGO_FUSED, ns.NS_FP64)
+    cases = [
+        (dict(dt=0.0), ns.NS_ERR_ARG),
+        (dict(dt=float("inf")), ns.NS_ERR_ARG),
+        (dict(nsteps=-1), ns.NS_ERR_ARG),
+        (dict(state=None), ns.NS_ERR_ARG),
+        (dict(work_bytes=wb - 1), ns.NS_ERR_WORKSPACE),
+        (dict(work=0x1010), ns.NS_ERR_WORKSPACE),          # misaligned
+        (dict(algo=ns.NS_ALGO_STORED, prec=ns.NS_FP32_STORE), ns.NS_ERR_UNSUPPORTED),
+        (dict(prec=5), ns.NS_ERR_ARG),
+    ]
+    for over, code in cases:
+        a = dict(algo=ns.NS_ALGO_FUSED, prec=ns.NS_FP64, dt=1e-3, nsteps=1, state=0x1000,
+                 work=0x100000, work_bytes=wb)
+        a.update(over)
+        with pytest.raises(ns.NativeError) as e:
+            ns.rk3_step(p, a["algo"], a["prec"], a["dt"], a["nsteps"], a["state"], a["work"],
+                        a["work_bytes"])
+        assert e.value.status == code, over
+
+
+def test_residual_rejects_overlap_and_small_work():
+    p = ns.make_params(16)
+    with pytest.raises(ns.NativeError) as e:
+        ns.ns_residual(p, ns.NS_ALGO_FUSED, 0x100000, 0x100000 + 8)
+    assert e.value.status == ns.NS_ERR_ARG
+    with pytest.raises(ns.NativeError) as e:
+        ns.ns_residual(p, ns.NS_ALGO_STORED, 0x100000, 0x10000000, 0x20000000, 1024)
+    assert e.value.status == ns.NS_ERR_WORKSPACE
+
+
+def test_fused_config_validation():
+    with pytest.raises(ns.NativeError):
+        ns.ns_set_fused_config(9, 0)
+    with pytest.raises(ns.NativeError):
+        ns.ns_set_fused_config(0, 2)
+    p = ns.make_params(64)
+    ns.ns_set_fused_config(1, 8)
+    assert ns.ns_get_fused_config(p) == (1, 8)
+    ns.ns_set_fused_config(-1, 0)
+    t, z = ns.ns_get_fused_config(p)
+    assert t == 0 and 4 <= z <= 64
+
+
+def test_package_has_no_cpu_fallback():
+    """The product package never imports the oracle."""
+    pkg = os.path.join(ROOT, "paper_1709_09713_amd")
+    for fn in os.listdir(pkg):
+        if fn.endswith(".py"):
+            src = open(os.path.join(pkg, fn)).read()
+            assert "oracle" not in src, fn
