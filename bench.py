@@ -184,7 +184,8 @@ def main():
         "config": {"workload": f"Taylor-Green vortex {n}^3, Re=1600, Pr=0.71, M=0.1, gamma=1.4, "
                                f"dt={run.dt:g}, {args.algo} {args.precision}",
                    "n": n, "algo": args.algo, "precision": args.precision,
-                   "tile_zchunk": list(ns.ns_get_fused_config(ns.make_params(n)))},
+                   "tile_zchunk": list(ns.ns_get_fused_config(ns.make_params(n),
+                                                              ns.PRECS[args.precision]))},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,

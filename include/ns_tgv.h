@@ -147,7 +147,8 @@ ns_status diagnostics(const ns_params *p, const double *state,
 
 /* Launch shape of the fused kernel, process-wide.  tile selects the
  * (x, y) column tile of one block: 0 = 32x8, 1 = 16x16, 2 = 64x4,
- * 3 = 32x16 (threads = product, one z column each); zchunk is the number of
+ * 3 = 32x16, 4 = 16x8, 5 = 32x4, 6 = 16x4, 7 = 8x8 (threads = product, one
+ * z column each); zchunk is the number of
  * z planes one block marches through (>= 4; 0 = automatic).  tile = -1
  * restores the automatic choice.  For a given tile, residuals and states
  * are bitwise independent of zchunk; different tiles are separate compiled
@@ -158,9 +159,9 @@ ns_status diagnostics(const ns_params *p, const double *state,
  * concurrent launches that expect a different shape. */
 ns_status ns_set_fused_config(int32_t tile, int32_t zchunk);
 
-/* The (tile, zchunk) the fused kernel would use for p right now. */
-ns_status ns_get_fused_config(const ns_params *p, int32_t *tile,
-                              int32_t *zchunk);
+/* The (tile, zchunk) the fused kernel would use for p and prec right now. */
+ns_status ns_get_fused_config(const ns_params *p, ns_precision prec,
+                              int32_t *tile, int32_t *zchunk);
 
 #ifdef __cplusplus
 }

@@ -32,7 +32,8 @@ NS_FP32_STORE = 1
 ALGOS = {"stored": NS_ALGO_STORED, "fused": NS_ALGO_FUSED}
 PRECS = {"fp64": NS_FP64, "fp32": NS_FP32_STORE}
 
-TILES = {0: (32, 8), 1: (16, 16), 2: (64, 4), 3: (32, 16)}
+TILES = {0: (32, 8), 1: (16, 16), 2: (64, 4), 3: (32, 16), 4: (16, 8), 5: (32, 4),
+         6: (16, 4), 7: (8, 8)}
 
 
 class ns_params(ctypes.Structure):
@@ -100,7 +101,8 @@ def lib():
         L.ns_set_fused_config.restype = ctypes.c_int
         L.ns_set_fused_config.argtypes = [i32, i32]
         L.ns_get_fused_config.restype = ctypes.c_int
-        L.ns_get_fused_config.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.ns_get_fused_config.argtypes = [P, ctypes.c_int, ctypes.POINTER(i32),
+                                          ctypes.POINTER(i32)]
         _lib = L
     return _lib
 
@@ -190,8 +192,8 @@ def ns_set_fused_config(tile: int, zchunk: int = 0):
     _check(lib().ns_set_fused_config(int(tile), int(zchunk)), "ns_set_fused_config")
 
 
-def ns_get_fused_config(p: ns_params):
+def ns_get_fused_config(p: ns_params, prec: int = NS_FP64):
     t, z = ctypes.c_int32(), ctypes.c_int32()
-    _check(lib().ns_get_fused_config(ctypes.byref(p), ctypes.byref(t), ctypes.byref(z)),
-           "ns_get_fused_config")
+    _check(lib().ns_get_fused_config(ctypes.byref(p), int(prec), ctypes.byref(t),
+                                     ctypes.byref(z)), "ns_get_fused_config")
     return t.value, z.value

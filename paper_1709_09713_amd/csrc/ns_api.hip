@@ -45,11 +45,13 @@ constexpr int kMinZChunk = 4;
 static std::atomic<int> g_tile{-1};
 static std::atomic<int> g_zchunk{0};
 
-static void choose_config(const Consts &c, int *tile, int *zchunk)
+// Default launch shape.  The z march is unrolled by 5 over zchunk + 4
+// planes, so chunks of 5k + 1 planes carry no padding planes.
+static void choose_config(const Consts &c, ns_precision prec, int *tile, int *zchunk)
 {
     int t = g_tile.load();
     int z = g_zchunk.load();
-    if (t < 0 || t >= TILE_COUNT) t = TILE_32x8;
+    if (t < 0 || t >= TILE_COUNT) t = (prec == NS_FP64) ? TILE_16x8 : TILE_32x8;
     if (z <= 0) {
         int bx, by;
         tile_dims(t, &bx, &by);
@@ -58,6 +60,7 @@ static void choose_config(const Consts &c, int *tile, int *zchunk)
         const int64_t nzc = (want + xy - 1) / xy;
         z = (int)((c.nz + nzc - 1) / nzc);
         if (z < 16) z = 16;
+        z = ((z + 3) / 5) * 5 + 1;
     }
     if (z < kMinZChunk) z = kMinZChunk;
     if (z > c.nz) z = c.nz;
@@ -193,13 +196,14 @@ ns_status ns_set_fused_config(int32_t tile, int32_t zchunk)
     return NS_OK;
 }
 
-ns_status ns_get_fused_config(const ns_params *p, int32_t *tile, int32_t *zchunk)
+ns_status ns_get_fused_config(const ns_params *p, ns_precision prec, int32_t *tile,
+                              int32_t *zchunk)
 {
     ns_status st = check_params(p);
     if (st != NS_OK) return st;
-    if (!tile || !zchunk) return NS_ERR_ARG;
+    if (!tile || !zchunk || !valid_prec(prec)) return NS_ERR_ARG;
     int t, z;
-    choose_config(make_consts(p), &t, &z);
+    choose_config(make_consts(p), prec, &t, &z);
     *tile = t;
     *zchunk = z;
     return NS_OK;
@@ -228,7 +232,7 @@ ns_status ns_residual(const ns_params *p, ns_algo algo, const double *Q, double 
     hipStream_t s = (hipStream_t)stream;
     if (algo == NS_ALGO_FUSED) {
         int tile, zc;
-        choose_config(c, &tile, &zc);
+        choose_config(c, NS_FP64, &tile, &zc);
         StageArgs a = {};
         a.qin = Q;
         a.rout = R;
@@ -265,7 +269,7 @@ ns_status rk3_step(const ns_params *p, ns_algo algo, ns_precision prec, double d
 
     if (algo == NS_ALGO_FUSED) {
         int tile, zc;
-        choose_config(c, &tile, &zc);
+        choose_config(c, prec, &tile, &zc);
         const int64_t nblk = fused_num_blocks(c, tile, zc);
         for (int32_t step = 0; step < nsteps; ++step) {
             StageArgs a = {};

@@ -59,6 +59,17 @@ __device__ __forceinline__ T d2u(T fm2, T fm1, T f0, T fp1, T fp2)
     return T(16) * (fm1 + fp1) - (fm2 + fp2) - T(30) * f0;
 }
 
+// Workgroup barrier that orders LDS only.  __syncthreads() is a release /
+// acquire fence over all address spaces, which makes every wave wait for its
+// outstanding global stores before the barrier; the stencil kernels only
+// need their LDS writes to be visible to the other waves of the block.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 }  // namespace ns
 
 #define NS_HIP_OK(expr)                                       \

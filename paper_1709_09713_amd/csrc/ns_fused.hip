@@ -4,7 +4,7 @@
 // (RA / SN / SN2): no derivative is written to a global array.  Every
 // derivative of the mass, momentum and energy equations (methodology
 // section; stencils fd and sd) is evaluated on the fly and accumulated
-// straight into the five residual registers of its grid point, and the
+// straight into the residual registers of its grid point, and the
 // low-storage RK3 update of the generic-algorithm figure is applied in the
 // same pass, so a stage reads its input once and writes its outputs once.
 //
@@ -12,25 +12,34 @@
 //  * A block owns a BX x BY column tile of the (x, y) plane and marches
 //    along z through a chunk of planes.  Each plane of the tile plus a
 //    radius-2 halo (wrap-around indexing replaces the periodic-boundary
-//    pass) is loaded with coalesced x-fastest loads, turned into the
-//    primitive variables once per point, and staged in LDS (double
-//    buffered, one barrier per plane).  x and y stencil taps are LDS reads.
-//  * z taps come from a per-thread register queue holding the thread's own
-//    column for planes z-2..z+2.
-//  * The in-plane part of the residual at plane z is computed while z is in
-//    LDS and carried in registers for two planes until the z taps of z+2
-//    arrive.  Mixed derivatives that involve z are taken as z-derivatives of
-//    in-plane derivatives (D_x D_z w = D_z D_x w, exact in exact arithmetic),
-//    so only three in-plane quantities (D_x u + D_y v, D_x w, D_y w) need a
-//    register queue; D_x D_y is a 16-tap LDS stencil.
-//  * Stage 1 can also emit the per-block partial sums of the diagnostics of
-//    its input state, so the per-step diagnostics cost no extra pass.
+//    pass) is loaded with coalesced x-fastest loads one plane ahead of its
+//    use (software prefetch into registers), turned into the primitive
+//    variables once per point, and staged in LDS (double buffered, one
+//    barrier per plane).  x and y stencil taps are LDS reads.
+//  * z derivatives whose coefficient is a constant (the flux divergences
+//    d(rho w)/dz, d(rho u_i w)/dz, dp/dz, d((rho E/2 + p) w)/dz and the heat
+//    conduction d2T/dz2) are scattered: as soon as a plane is staged its
+//    values are added, with the stencil weights, into a five-deep ring of
+//    pending residual accumulators of the planes two below to two above it
+//    (linearity lets terms that share a coefficient share one stencil).
+//  * z derivatives multiplied by point values (w d(rho, rho u_i, rho E)/dz,
+//    the velocity gradient, the viscous terms) are gathered at the output
+//    plane from a five-deep register ring of (rho, rho E, u, v, w).
+//  * Mixed derivatives that involve z are taken as z-derivatives of in-plane
+//    derivatives (D_x D_z w = D_z D_x w, exact in exact arithmetic), so
+//    three in-plane quantities (D_x u + D_y v, D_x w, D_y w) get a ring;
+//    D_x D_y is a 16-tap LDS stencil.
+//  * The march is unrolled by the ring depth (5) so every ring slot is a
+//    compile-time register: no rotation moves.
+//  * Stage 1 can also emit per-block partial sums of the diagnostics of its
+//    input state, so the per-step diagnostics cost no extra pass.
 //
 // Precision: CT is the stencil/residual arithmetic type.  With CT = float
 // (FP32 storage) the staged fields are deviations from the uniform
 // reference state (rho - 1, rhoE - rhoE_ref, p - p_ref, T - 1); the constant
-// parts are applied analytically (stencil coefficients sum to zero), and the
-// RK accumulator stays double.
+// parts are applied analytically (stencil coefficients sum to zero: only
+// H_ref div u survives, added in double), and the RK accumulator stays
+// double.
 #include <type_traits>
 
 #include "ns_common.hpp"
@@ -39,15 +48,14 @@
 namespace ns {
 
 template <typename TIN, typename CT>
-__device__ __forceinline__ CT load_dev(const TIN *q, int64_t i, double ref)
+__device__ __forceinline__ CT to_ct(TIN v, double ref)
 {
-    if constexpr (std::is_same<CT, double>::value) {
-        return q[i];
-    } else if constexpr (std::is_same<TIN, double>::value) {
-        return (float)(q[i] - ref);
-    } else {
-        return q[i];
-    }
+    if constexpr (std::is_same<CT, double>::value)
+        return v;
+    else if constexpr (std::is_same<TIN, double>::value)
+        return (float)(v - ref);
+    else
+        return v;
 }
 
 template <typename TOUT>
@@ -59,7 +67,10 @@ __device__ __forceinline__ void store_q(void *q, int64_t i, double v, double ref
         ((float *)q)[i] = (float)(v - ref);
 }
 
-template <int BX, int BY, typename TIN, typename TOUT, typename CT>
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+template <int BX, int BY, typename TIN, typename TOUT, typename CT, bool DIAG>
 __global__ void __launch_bounds__(BX * BY)
 fused_stage_kernel(Consts c, StageArgs s)
 {
@@ -67,6 +78,7 @@ fused_stage_kernel(Consts c, StageArgs s)
     constexpr int HX = BX + 4, HY = BY + 4, HP = HX * HY, NT = BX * BY;
     constexpr int NLOAD = (HP + NT - 1) / NT;
     enum { L_RHO, L_M0, L_M1, L_M2, L_E, L_U, L_V, L_W, L_P, L_T, NF };
+    enum { Z_RHO, Z_E, Z_U, Z_V, Z_W, NZ };
     __shared__ CT lds[2][NF][HP];
     __shared__ double red[NT / 64 + 1][kDiag];
 
@@ -79,7 +91,8 @@ fused_stage_kernel(Consts c, StageArgs s)
     const int own = (ty + 2) * HX + tx + 2;
     const int64_t N = c.N;
     const TIN *qin = (const TIN *)s.qin;
-    const bool want_diag = s.diag_partial != nullptr;
+    constexpr int NR = DIAG ? 6 : 5;    // ring entries: residuals (+ omega_z)
+    const int64_t col = (int64_t)gy * c.nx + gx;   // own (x, y) offset in a plane
 
     // Plane offsets of the points this thread loads (fixed for the march).
     int loff[NLOAD];
@@ -103,38 +116,51 @@ fused_stage_kernel(Consts c, StageArgs s)
     const CT gm1 = (CT)c.gm1, gM2 = (CT)c.gM2;
     const CT half = CT(0.5), third = CT(1) / CT(3), four3 = CT(4) / CT(3);
     const CT two3 = CT(2) / CT(3);
+    const CT kz = kappa * c2z;
 
-    CT qv[5][NF];                 // own column, planes zp-4 .. zp
-    CT qa[5], qb[5], qc[5];       // D_x u + D_y v, D_x w, D_y w at zp-4 .. zp
-    CT pr[3][6];                  // in-plane partial residual + omega_z, zp-2 .. zp
-    double dsum[7] = {0, 0, 0, 0, 0, 0, 0};
+    CT qz[5][NZ];                 // ring: (rho, rhoE, u, v, w) of the own column
+    CT qa[5], qb[5], qc[5];       // ring: D_x u + D_y v, D_x w, D_y w
+    CT ra[5][NR];                 // ring: pending residuals (5) (+ omega_z)
+    TIN pf[NLOAD][5];             // next plane, prefetched
+    double accpf[5];              // accumulator (or exact state) of the output point
+    double dsum[DIAG ? 7 : 1];
+#pragma unroll
+    for (int k = 0; k < (DIAG ? 7 : 1); ++k) dsum[k] = 0.0;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         qa[q] = qb[q] = qc[q] = CT(0);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) qv[q][f] = CT(0);
+        for (int f = 0; f < NZ; ++f) qz[q][f] = CT(0);
+#pragma unroll
+        for (int f = 0; f < NR; ++f) ra[q][f] = CT(0);
     }
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-#pragma unroll
-        for (int f = 0; f < 6; ++f) pr[q][f] = CT(0);
 
-    for (int zp = z0 - 2; zp < z1 + 2; ++zp) {
-        const int b = (zp - z0) & 1;
-        const int zw = wrap1(zp, c.nz);
+    auto load_plane = [&](int zp) {
+        // zp is in [-2, nz + 6] (march padding): at most two wraps
+        int zw = zp < 0 ? zp + c.nz : zp;
+        zw = zw >= c.nz ? zw - c.nz : zw;
+        zw = zw >= c.nz ? zw - c.nz : zw;
         const int64_t base = (int64_t)zw * c.nxy;
-
-        // ---- stage plane zp (tile + halo): conserved -> primitives -> LDS
+        // every slot loads (idle slots read a valid point they never use):
+        // unconditional loads keep the wait counts exact
+#pragma unroll
+        for (int r = 0; r < NLOAD; ++r) {
+            const int64_t g = base + loff[r];
+#pragma unroll
+            for (int f = 0; f < 5; ++f) pf[r][f] = qin[g + f * N];
+        }
+    };
+    // conserved (pf) -> primitives -> LDS buffer b
+    auto stage_plane = [&](int b) {
 #pragma unroll
         for (int r = 0; r < NLOAD; ++r) {
             const int idx = tid + r * NT;
             if (idx < HP) {
-                const int64_t g = base + loff[r];
-                const CT rho = load_dev<TIN, CT>(qin, g, c.rho_ref);
-                const CT m0 = load_dev<TIN, CT>(qin, g + N, 0.0);
-                const CT m1 = load_dev<TIN, CT>(qin, g + 2 * N, 0.0);
-                const CT m2 = load_dev<TIN, CT>(qin, g + 3 * N, 0.0);
-                const CT E = load_dev<TIN, CT>(qin, g + 4 * N, c.rhoE_ref);
+                const CT rho = to_ct<TIN, CT>(pf[r][0], c.rho_ref);
+                const CT m0 = to_ct<TIN, CT>(pf[r][1], 0.0);
+                const CT m1 = to_ct<TIN, CT>(pf[r][2], 0.0);
+                const CT m2 = to_ct<TIN, CT>(pf[r][3], 0.0);
+                const CT E = to_ct<TIN, CT>(pf[r][4], c.rhoE_ref);
                 const CT rhof = DEV ? CT(1) + rho : rho;
                 const CT inv = CT(1) / rhof;
                 const CT u = m0 * inv, v = m1 * inv, w = m2 * inv;
@@ -154,7 +180,38 @@ fused_stage_kernel(Consts c, StageArgs s)
                 lds[b][L_T][idx] = T;
             }
         }
-        __syncthreads();
+    };
+
+    // One plane of the march.  PH = (zp - z0 + 2) mod 5 selects ring slots:
+    // plane zp + k lives in slot (PH + k) mod 5.
+    auto step = [&](auto phc, int zp) {
+        constexpr int PH = decltype(phc)::value;
+        constexpr int SM2 = (PH + 3) % 5, SM1 = (PH + 4) % 5, S0 = PH;
+        constexpr int SP1 = (PH + 1) % 5, SP2 = (PH + 2) % 5;
+        constexpr int SM4 = (PH + 1) % 5, SM3 = (PH + 2) % 5;   // zp-4, zp-3
+        const int b = (zp - z0) & 1;
+        const int zf = zp - 2;
+        const bool fin = active && zf >= z0 && zf < z1;
+
+        // issue the loads of the output point's accumulator and of the next
+        // plane; they complete while this plane is computed.  Loads and
+        // stores retire in issue order, so the accumulator (needed first)
+        // is requested first.
+        {
+            // stages 2 and 3 read the accumulator; the residual and stage 1
+            // read the exact double input state (unused for the residual).
+            // Threads with no output point read a valid address they ignore.
+            const double *src = (s.mode >= 2) ? s.acc_in : (const double *)s.qin;
+            const int zc = fin ? zf : z0;
+            const int64_t pidx = (int64_t)zc * c.nxy + (active ? col : 0);
+#pragma unroll
+            for (int f = 0; f < 5; ++f) accpf[f] = src[f * N + pidx];
+        }
+        load_plane(zp + 1);
+
+        // the slot of plane zp + 2 is free (plane zp - 3 was finished)
+#pragma unroll
+        for (int f = 0; f < NR; ++f) ra[SP2][f] = CT(0);
 
 #define LV(f, dy, dx) lds[b][f][own + (dy) * HX + (dx)]
 #define DX1(f) d1u(LV(f, 0, -2), LV(f, 0, -1), LV(f, 0, 1), LV(f, 0, 2))
@@ -165,6 +222,10 @@ fused_stage_kernel(Consts c, StageArgs s)
 #define DY1P(f, g)                                                       \
     d1u(LV(f, -2, 0) * LV(g, -2, 0), LV(f, -1, 0) * LV(g, -1, 0),        \
         LV(f, 1, 0) * LV(g, 1, 0), LV(f, 2, 0) * LV(g, 2, 0))
+// (rhoE/2 + p) u_j at a tap: energy flux of the x or y direction
+#define HF(dy, dx, g) ((half * LV(L_E, dy, dx) + LV(L_P, dy, dx)) * LV(g, dy, dx))
+#define DX1H() d1u(HF(0, -2, L_U), HF(0, -1, L_U), HF(0, 1, L_U), HF(0, 2, L_U))
+#define DY1H() d1u(HF(-2, 0, L_V), HF(-1, 0, L_V), HF(1, 0, L_V), HF(2, 0, L_V))
 #define DX2(f) d2u(LV(f, 0, -2), LV(f, 0, -1), LV(f, 0, 0), LV(f, 0, 1), LV(f, 0, 2))
 #define DY2(f) d2u(LV(f, -2, 0), LV(f, -1, 0), LV(f, 0, 0), LV(f, 1, 0), LV(f, 2, 0))
 // D_x applied to D_y f (16 taps), unscaled.
@@ -180,187 +241,198 @@ fused_stage_kernel(Consts c, StageArgs s)
         d1u(LV(f, 1, -2), LV(f, 1, -1), LV(f, 1, 1), LV(f, 1, 2)),       \
         d1u(LV(f, 2, -2), LV(f, 2, -1), LV(f, 2, 1), LV(f, 2, 2)))
 
-        // ---- in-plane part at plane zp
-        CT cen[NF];
-        CT na = CT(0), nb = CT(0), nc = CT(0);
-        CT np[6] = {CT(0), CT(0), CT(0), CT(0), CT(0), CT(0)};
         if (active) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) cen[f] = LV(f, 0, 0);
+            const CT rho = LV(L_RHO, 0, 0), E = LV(L_E, 0, 0);
+            const CT m0 = LV(L_M0, 0, 0), m1 = LV(L_M1, 0, 0), m2 = LV(L_M2, 0, 0);
+            const CT u = LV(L_U, 0, 0), v = LV(L_V, 0, 0), w = LV(L_W, 0, 0);
+            const CT p = LV(L_P, 0, 0), T = LV(L_T, 0, 0);
             const CT Gxx = c1x * DX1(L_U), Gxy = c1y * DY1(L_U);
             const CT Gyx = c1x * DX1(L_V), Gyy = c1y * DY1(L_V);
             const CT Gzx = c1x * DX1(L_W), Gzy = c1y * DY1(L_W);
-            na = Gxx + Gyy;
-            nb = Gzx;
-            nc = Gzy;
-            if (zp >= z0 && zp < z1) {
-                const CT rho = cen[L_RHO], E = cen[L_E];
-                const CT u = cen[L_U], v = cen[L_V], w = cen[L_W];
-                const CT rhof = DEV ? CT(1) + rho : rho;
-                const CT a = na;
-                // mass: -1/2 (d(rho u_j)/dx_j + rho du_j/dx_j + u_j drho/dx_j), j = x, y
-                np[0] = -half * (c1x * DX1(L_M0) + c1y * DY1(L_M1) + rhof * a
-                                 + u * (c1x * DX1(L_RHO)) + v * (c1y * DY1(L_RHO)));
-                // momentum convection and pressure gradient, j = x, y
+            const CT a = Gxx + Gyy;
+            qz[S0][Z_RHO] = rho;
+            qz[S0][Z_E] = E;
+            qz[S0][Z_U] = u;
+            qz[S0][Z_V] = v;
+            qz[S0][Z_W] = w;
+            qa[S0] = a;
+            qb[S0] = Gzx;
+            qc[S0] = Gzy;
+
+            // scatter the constant-coefficient z fluxes of this plane
+            const CT g0 = -half * c1z * m2;                  // -1/2 d(rho w)/dz
+            const CT g1 = -half * c1z * (m0 * w);            // -1/2 d(rho u w)/dz
+            const CT g2 = -half * c1z * (m1 * w);            // -1/2 d(rho v w)/dz
+            const CT g3 = -c1z * (half * (m2 * w) + p);      // -1/2 d(rho w w)/dz - dp/dz
+            const CT g4 = -c1z * ((half * E + p) * w);       // -1/2 d(rhoE w)/dz - d(p w)/dz
+            const CT gT = kz * T;                            // kappa d2T/dz2
+            const CT g[5] = {g0, g1, g2, g3, g4};
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const int Lm = L_M0 + i;
-                    np[1 + i] = -half * (c1x * DX1P(Lm, L_U) + c1y * DY1P(Lm, L_V)
-                                         + cen[Lm] * a + u * (c1x * DX1(Lm))
-                                         + v * (c1y * DY1(Lm)));
-                }
-                np[1] -= c1x * DX1(L_P);
-                np[2] -= c1y * DY1(L_P);
+            for (int f = 0; f < 5; ++f) {
+                ra[SM2][f] -= g[f];
+                ra[SM1][f] += CT(8) * g[f];
+                ra[SP1][f] -= CT(8) * g[f];
+                ra[SP2][f] += g[f];
+            }
+            ra[SM2][4] -= gT;
+            ra[SM1][4] += CT(16) * gT;
+            ra[S0][4] -= CT(30) * gT;
+            ra[SP1][4] += CT(16) * gT;
+            ra[SP2][4] -= gT;
+
+            if (zp >= z0 && zp < z1) {
+                // in-plane (x, y) part of the residual of this plane
+                const CT rhof = DEV ? CT(1) + rho : rho;
+                const CT uc = u * c1x, vc = v * c1y;
+                ra[S0][0] -= half * (c1x * DX1(L_M0) + c1y * DY1(L_M1) + rhof * a
+                                     + uc * DX1(L_RHO) + vc * DY1(L_RHO));
+                ra[S0][1] -= half * (c1x * DX1P(L_M0, L_U) + c1y * DY1P(L_M0, L_V) + m0 * a
+                                     + uc * DX1(L_M0) + vc * DY1(L_M0))
+                             + c1x * DX1(L_P);
+                ra[S0][2] -= half * (c1x * DX1P(L_M1, L_U) + c1y * DY1P(L_M1, L_V) + m1 * a
+                                     + uc * DX1(L_M1) + vc * DY1(L_M1))
+                             + c1y * DY1(L_P);
+                ra[S0][3] -= half * (c1x * DX1P(L_M2, L_U) + c1y * DY1P(L_M2, L_V) + m2 * a
+                                     + uc * DX1(L_M2) + vc * DY1(L_M2));
                 // viscous: d_j tau_ij = lap u_i + (1/3) d_i div u, in-plane parts
                 const CT Vx = four3 * (c2x * DX2(L_U)) + c2y * DY2(L_U)
                               + third * (c1x * c1y * DXDY(L_V));
                 const CT Vy = c2x * DX2(L_V) + four3 * (c2y * DY2(L_V))
                               + third * (c1x * c1y * DYDX(L_U));
                 const CT Vz = c2x * DX2(L_W) + c2y * DY2(L_W);
-                np[1] += inv_re * Vx;
-                np[2] += inv_re * Vy;
-                np[3] += inv_re * Vz;
+                ra[S0][1] += inv_re * Vx;
+                ra[S0][2] += inv_re * Vy;
+                ra[S0][3] += inv_re * Vz;
                 // tau_ij du_i/dx_j restricted to terms without a z derivative
                 const CT phi = CT(2) * (Gxx * Gxx + Gyy * Gyy) + Gxy * Gxy + Gyx * Gyx
                                + CT(2) * Gxy * Gyx + Gzx * Gzx + Gzy * Gzy;
                 // energy: skew convection, pressure work, viscous work,
-                // dissipation and heat conduction, j = x, y.  The constant
-                // part H_ref * div of the FP32 deviation form is added in
-                // double at the end.
-                np[4] = -half * (c1x * DX1P(L_E, L_U) + c1y * DY1P(L_E, L_V) + E * a
-                                 + u * (c1x * DX1(L_E)) + v * (c1y * DY1(L_E)))
-                        - (c1x * DX1P(L_P, L_U) + c1y * DY1P(L_P, L_V))
-                        + inv_re * (u * Vx + v * Vy + w * Vz + phi)
-                        + kappa * (c2x * DX2(L_T) + c2y * DY2(L_T));
-                np[5] = Gyx - Gxy;   // omega_z, for the diagnostics
+                // dissipation, heat conduction (x, y)
+                ra[S0][4] += -(c1x * DX1H() + c1y * DY1H())
+                             - half * (E * a + uc * DX1(L_E) + vc * DY1(L_E))
+                             + inv_re * (u * Vx + v * Vy + w * Vz + phi)
+                             + kappa * (c2x * DX2(L_T) + c2y * DY2(L_T));
+                if constexpr (DIAG) ra[S0][NR - 1] = Gyx - Gxy;   // omega_z
             }
-        } else {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) cen[f] = CT(0);
         }
 #undef LV
 #undef DX1
 #undef DY1
 #undef DX1P
 #undef DY1P
+#undef HF
+#undef DX1H
+#undef DY1H
 #undef DX2
 #undef DY2
 #undef DXDY
 #undef DYDX
 
-        // ---- advance the register queues
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) qv[q][f] = qv[q + 1][f];
-            qa[q] = qa[q + 1];
-            qb[q] = qb[q + 1];
-            qc[q] = qc[q + 1];
-        }
-#pragma unroll
-        for (int f = 0; f < NF; ++f) qv[4][f] = cen[f];
-        qa[4] = na;
-        qb[4] = nb;
-        qc[4] = nc;
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            pr[0][f] = pr[1][f];
-            pr[1][f] = pr[2][f];
-            pr[2][f] = np[f];
-        }
+        // ---- stage plane zp + 1 into the other LDS buffer (last read in the
+        // previous step, before its barrier); done before the output stores
+        // so that waiting for the prefetched loads never waits for stores
+        stage_plane(b ^ 1);
 
-        // ---- finish plane zf = zp - 2: z derivatives, RK update, output
-        const int zf = zp - 2;
-        if (active && zf >= z0 && zf < z1) {
-#define DZ1(f) d1u(qv[0][f], qv[1][f], qv[3][f], qv[4][f])
-#define DZ1P(f, g) \
-    d1u(qv[0][f] * qv[0][g], qv[1][f] * qv[1][g], qv[3][f] * qv[3][g], qv[4][f] * qv[4][g])
-#define DZ2(f) d2u(qv[0][f], qv[1][f], qv[2][f], qv[3][f], qv[4][f])
-            const CT rho = qv[2][L_RHO], E = qv[2][L_E];
-            const CT u = qv[2][L_U], v = qv[2][L_V], w = qv[2][L_W];
+        // ---- finish plane zf = zp - 2: gathered z terms, RK update, output
+        if (fin) {
+#define DZ1(f) d1u(qz[SM4][f], qz[SM3][f], qz[SM1][f], qz[S0][f])
+#define DZ2(f) d2u(qz[SM4][f], qz[SM3][f], qz[SM2][f], qz[SM1][f], qz[S0][f])
+#define DZM(k)                                                                       \
+    d1u(qz[SM4][Z_RHO] * qz[SM4][k], qz[SM3][Z_RHO] * qz[SM3][k],                    \
+        qz[SM1][Z_RHO] * qz[SM1][k], qz[S0][Z_RHO] * qz[S0][k])
+            const CT rho = qz[SM2][Z_RHO], E = qz[SM2][Z_E];
+            const CT u = qz[SM2][Z_U], v = qz[SM2][Z_V], w = qz[SM2][Z_W];
             const CT rhof = DEV ? CT(1) + rho : rho;
-            const CT a = qa[2], bb = qb[2], cc = qc[2];
-            const CT Gxz = c1z * DZ1(L_U), Gyz = c1z * DZ1(L_V), Gzz = c1z * DZ1(L_W);
-            const CT Da = c1z * d1u(qa[0], qa[1], qa[3], qa[4]);
-            const CT Db = c1z * d1u(qb[0], qb[1], qb[3], qb[4]);
-            const CT Dc = c1z * d1u(qc[0], qc[1], qc[3], qc[4]);
-
+            const CT a = qa[SM2], bb = qb[SM2], cc = qc[SM2];
+            const CT wc = w * c1z;
+            const CT Gxz = c1z * DZ1(Z_U), Gyz = c1z * DZ1(Z_V), Gzz = c1z * DZ1(Z_W);
+            const CT Da = c1z * d1u(qa[SM4], qa[SM3], qa[SM1], qa[S0]);
+            const CT Db = c1z * d1u(qb[SM4], qb[SM3], qb[SM1], qb[S0]);
+            const CT Dc = c1z * d1u(qc[SM4], qc[SM3], qc[SM1], qc[S0]);
+            // rho u_i at the z taps (m_i = rho u_i; in the deviation form
+            // rho is 1 + rho')
             CT R[5];
-            R[0] = pr[0][0] - half * (c1z * DZ1(L_M2) + rhof * Gzz + w * (c1z * DZ1(L_RHO)));
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const int Lm = L_M0 + i;
-                R[1 + i] = pr[0][1 + i]
-                           - half * (c1z * DZ1P(Lm, L_W) + qv[2][Lm] * Gzz
-                                     + w * (c1z * DZ1(Lm)));
+            R[0] = ra[SM2][0] - half * (rhof * Gzz + wc * DZ1(Z_RHO));
+            if constexpr (DEV) {
+#define DZMD(k)                                                                                    \
+    d1u((CT(1) + qz[SM4][Z_RHO]) * qz[SM4][k], (CT(1) + qz[SM3][Z_RHO]) * qz[SM3][k],              \
+        (CT(1) + qz[SM1][Z_RHO]) * qz[SM1][k], (CT(1) + qz[S0][Z_RHO]) * qz[S0][k])
+                R[1] = ra[SM2][1] - half * (rhof * u * Gzz + wc * DZMD(Z_U));
+                R[2] = ra[SM2][2] - half * (rhof * v * Gzz + wc * DZMD(Z_V));
+                R[3] = ra[SM2][3] - half * (rhof * w * Gzz + wc * DZMD(Z_W));
+#undef DZMD
+            } else {
+                R[1] = ra[SM2][1] - half * (rhof * u * Gzz + wc * DZM(Z_U));
+                R[2] = ra[SM2][2] - half * (rhof * v * Gzz + wc * DZM(Z_V));
+                R[3] = ra[SM2][3] - half * (rhof * w * Gzz + wc * DZM(Z_W));
             }
-            R[3] -= c1z * DZ1(L_P);
-            const CT Vx = c2z * DZ2(L_U) + third * Db;
-            const CT Vy = c2z * DZ2(L_V) + third * Dc;
-            const CT Vz = four3 * (c2z * DZ2(L_W)) + third * Da;
+            const CT Vx = c2z * DZ2(Z_U) + third * Db;
+            const CT Vy = c2z * DZ2(Z_V) + third * Dc;
+            const CT Vz = four3 * (c2z * DZ2(Z_W)) + third * Da;
             R[1] += inv_re * Vx;
             R[2] += inv_re * Vy;
             R[3] += inv_re * Vz;
             const CT div = a + Gzz;
             const CT phi = Gxz * Gxz + Gyz * Gyz + CT(2) * Gzz * Gzz
                            + CT(2) * (Gxz * bb + Gyz * cc) - two3 * div * div;
-            R[4] = pr[0][4]
-                   - half * (c1z * DZ1P(L_E, L_W) + E * Gzz + w * (c1z * DZ1(L_E)))
-                   - c1z * DZ1P(L_P, L_W)
-                   + inv_re * (u * Vx + v * Vy + w * Vz + phi)
-                   + kappa * (c2z * DZ2(L_T));
-
+            R[4] = ra[SM2][4] - half * (E * Gzz + wc * DZ1(Z_E))
+                   + inv_re * (u * Vx + v * Vy + w * Vz + phi);
+#undef DZ1
+#undef DZ2
+#undef DZM
             double Rd[5];
 #pragma unroll
             for (int f = 0; f < 5; ++f) Rd[f] = (double)R[f];
             if constexpr (DEV) Rd[4] -= c.H_ref * ((double)a + (double)Gzz);
 
-            const int64_t pidx = (int64_t)zf * c.nxy + (int64_t)gy * c.nx + gx;
+            const int64_t pidx = (int64_t)zf * c.nxy + col;
             if (s.mode == 0) {
 #pragma unroll
                 for (int f = 0; f < 5; ++f) s.rout[f * N + pidx] = Rd[f];
             } else {
                 const double ref[5] = {c.rho_ref, 0.0, 0.0, 0.0, c.rhoE_ref};
-                double acc[5];
-                if (s.mode == 1) {
-                    if constexpr (DEV) {
-                        // exact double state: re-read (TIN is double in stage 1)
+                if constexpr (DIAG) {
+                    // diagnostics of the stage input (the state at step
+                    // start): conserved totals from the exact double state,
+                    // kinetic energy and enstrophy from the staged
+                    // primitives and gradients
+                    const CT ox = cc - Gyz, oy = Gxz - bb, oz = ra[SM2][NR - 1];
 #pragma unroll
-                        for (int f = 0; f < 5; ++f)
-                            acc[f] = ((const double *)s.qin)[f * N + pidx];
-                    } else {
-#pragma unroll
-                        for (int f = 0; f < 5; ++f) acc[f] = (double)qv[2][L_RHO + f];
-                    }
-                    if (want_diag) {
-                        // diagnostics of the stage input (the state at step
-                        // start): conserved totals from the exact double
-                        // state, kinetic energy and enstrophy from the staged
-                        // primitives and gradients
-                        const CT ox = cc - Gyz, oy = Gxz - bb, oz = pr[0][5];
-#pragma unroll
-                        for (int f = 0; f < 5; ++f) dsum[f] += acc[f];
-                        dsum[5] += 0.5 * (acc[1] * (double)u + acc[2] * (double)v + acc[3] * (double)w);
-                        dsum[6] += 0.5 * (double)rhof * ((double)ox * (double)ox + (double)oy * (double)oy
-                                                         + (double)oz * (double)oz);
-                    }
-                } else {
-#pragma unroll
-                    for (int f = 0; f < 5; ++f) acc[f] = s.acc_in[f * N + pidx];
+                    for (int f = 0; f < 5; ++f) dsum[f] += accpf[f];
+                    dsum[5] += 0.5 * (accpf[1] * (double)u + accpf[2] * (double)v
+                                      + accpf[3] * (double)w);
+                    dsum[6] += 0.5 * (double)rhof * ((double)ox * (double)ox + (double)oy * (double)oy
+                                                     + (double)oz * (double)oz);
                 }
 #pragma unroll
                 for (int f = 0; f < 5; ++f) {
-                    store_q<TOUT>(s.qout, f * N + pidx, acc[f] + s.a_dt * Rd[f], ref[f]);
-                    if (s.mode < 3) s.acc_out[f * N + pidx] = acc[f] + s.b_dt * Rd[f];
+                    store_q<TOUT>(s.qout, f * N + pidx, accpf[f] + s.a_dt * Rd[f], ref[f]);
+                    if (s.mode < 3) s.acc_out[f * N + pidx] = accpf[f] + s.b_dt * Rd[f];
                 }
             }
-#undef DZ1
-#undef DZ1P
-#undef DZ2
         }
+
+        lds_barrier();
+    };
+
+    // prologue: plane z0 - 2 into LDS buffer 0
+    load_plane(z0 - 2);
+    stage_plane(0);
+    lds_barrier();
+
+    // The march covers planes z0-2 .. z1+1, padded to a multiple of 5;
+    // padding planes are loaded (wrapped, valid memory) but never output.
+    const int L = z1 - z0 + 4;
+    for (int it = 0; it < L; it += 5) {
+        const int zp = z0 - 2 + it;
+        step(IC<0>{}, zp);
+        step(IC<1>{}, zp + 1);
+        step(IC<2>{}, zp + 2);
+        step(IC<3>{}, zp + 3);
+        step(IC<4>{}, zp + 4);
     }
 
-    if (want_diag) {
+    if constexpr (DIAG) {
         // block reduction of the diagnostic partial sums, fixed order
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
@@ -395,7 +467,16 @@ static hipError_t launch_t(const Consts &c, const StageArgs &s, hipStream_t st)
 {
     dim3 block(BX, BY, 1);
     dim3 grid((c.nx + BX - 1) / BX, (c.ny + BY - 1) / BY, (c.nz + s.zchunk - 1) / s.zchunk);
-    hipLaunchKernelGGL((fused_stage_kernel<BX, BY, TIN, TOUT, CT>), grid, block, 0, st, c, s);
+    // per-step diagnostics are only taken in stage 1, which reads the
+    // double state
+    if constexpr (std::is_same<TIN, double>::value) {
+        if (s.diag_partial != nullptr && s.mode == 1) {
+            hipLaunchKernelGGL((fused_stage_kernel<BX, BY, TIN, TOUT, CT, true>), grid, block, 0, st,
+                               c, s);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((fused_stage_kernel<BX, BY, TIN, TOUT, CT, false>), grid, block, 0, st, c, s);
     return hipGetLastError();
 }
 
@@ -407,6 +488,10 @@ static hipError_t launch_tile(int tile, const Consts &c, const StageArgs &s, hip
     case TILE_16x16: return launch_t<16, 16, TIN, TOUT, CT>(c, s, st);
     case TILE_64x4: return launch_t<64, 4, TIN, TOUT, CT>(c, s, st);
     case TILE_32x16: return launch_t<32, 16, TIN, TOUT, CT>(c, s, st);
+    case TILE_16x8: return launch_t<16, 8, TIN, TOUT, CT>(c, s, st);
+    case TILE_32x4: return launch_t<32, 4, TIN, TOUT, CT>(c, s, st);
+    case TILE_16x4: return launch_t<16, 4, TIN, TOUT, CT>(c, s, st);
+    case TILE_8x8: return launch_t<8, 8, TIN, TOUT, CT>(c, s, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -417,6 +502,10 @@ void tile_dims(int tile, int *bx, int *by)
     case TILE_16x16: *bx = 16; *by = 16; break;
     case TILE_64x4: *bx = 64; *by = 4; break;
     case TILE_32x16: *bx = 32; *by = 16; break;
+    case TILE_16x8: *bx = 16; *by = 8; break;
+    case TILE_32x4: *bx = 32; *by = 4; break;
+    case TILE_16x4: *bx = 16; *by = 4; break;
+    case TILE_8x8: *bx = 8; *by = 8; break;
     default: *bx = 32; *by = 8; break;
     }
 }

@@ -7,7 +7,10 @@ namespace ns {
 
 // Column-tile shapes of the fused kernel (threads = BX * BY, one z column
 // each).  Chosen per problem by the autotuner or by the default rule.
-enum { TILE_32x8 = 0, TILE_16x16 = 1, TILE_64x4 = 2, TILE_32x16 = 3, TILE_COUNT = 4 };
+enum {
+    TILE_32x8 = 0, TILE_16x16 = 1, TILE_64x4 = 2, TILE_32x16 = 3,
+    TILE_16x8 = 4, TILE_32x4 = 5, TILE_16x4 = 6, TILE_8x8 = 7, TILE_COUNT = 8
+};
 
 // One fused launch: residual only (mode 0) or RK stage 1..3.
 struct StageArgs {
