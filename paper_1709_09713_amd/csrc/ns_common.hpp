@@ -59,6 +59,26 @@ __device__ __forceinline__ T d2u(T fm2, T fm1, T f0, T fp1, T fp2)
     return T(16) * (fm1 + fp1) - (fm2 + fp2) - T(30) * f0;
 }
 
+// XCD-aware tile order.  The dispatcher hands workgroups to the 8 XCDs
+// round-robin by linear workgroup id, and each XCD has its own L2.  Remap so
+// that XCD k processes the k-th contiguous run of tiles (x fastest, then y,
+// then z): tiles that share halo rows and columns then run at the same time
+// on the same L2.  Bijective for any grid size.
+constexpr int kNumXcd = 8;
+
+__device__ __forceinline__ void xcd_tile(int *bx, int *by, int *bz)
+{
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int total = gx * gy * gridDim.z;
+    const int L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int k = L % kNumXcd, slot = L / kNumXcd;
+    const int q = total / kNumXcd, r = total % kNumXcd;
+    const int T = k * q + min(k, r) + slot;
+    *bx = T % gx;
+    *by = (T / gx) % gy;
+    *bz = T / (gx * gy);
+}
+
 // Workgroup barrier that orders LDS only.  __syncthreads() is a release /
 // acquire fence over all address spaces, which makes every wave wait for its
 // outstanding global stores before the barrier; the stencil kernels only
