@@ -11,7 +11,11 @@ run on, bracketed by device synchronisation.
 Prints one JSON line.  Extra keys: ``roofline`` (dominant kernel: the fused
 stage kernel), ``cpu_baseline`` (the FP64 oracle on the host cores, one RK3
 step of the same workload), ``variants`` (stored-derivative class,
-FP32 storage, and the 512^3 fused-vs-stored comparison).
+FP32 storage, and the 512^3 fused-vs-stored comparison), ``batched`` (64
+independent TGV instances of mixed sizes, FP32 storage, autotuned launch
+shapes, against the same instances solved one after another in FP64) and
+``serving`` (a Poisson request stream through the continuous-batching
+server, p50/p99 latency and throughput, against sequential FP64 solves).
 """
 from __future__ import annotations
 
@@ -95,6 +99,88 @@ def cpu_baseline(n, steps=1):
             f"OpenMP over z-planes), {sec:.1f} s"}
 
 
+def batched(tuner, seed=0, count=64, steps=200):
+    """64 independent TGV instances (N from {32,48,64,96,128}, Re ~ U[400,
+    3200], M ~ U[0.05, 0.4]), `steps` RK3 steps each: one batch in FP32
+    storage with autotuned launch shapes, the same batch in FP64, and the
+    instances solved one after another with rk3_step in FP64."""
+    insts = synth.batch_instances(seed, count, steps=steps)
+    upd = sum(i["n"] ** 3 * 3 * i["steps"] for i in insts)
+    out = {"instances": count, "seed": seed, "steps": steps, "updates": upd,
+           "total_points": sum(i["n"] ** 3 for i in insts)}
+    stream = torch.cuda.current_stream()
+    for prec in ("fp32", "fp64"):
+        b = ns.Batch(count, prec, nstreams=4)
+        for i in insts:
+            tile, zc = tuner.lookup(i["n"], prec)
+            b.add(i["n"], reynolds=i["reynolds"], mach=i["mach"], dt=i["dt"], steps=i["steps"],
+                  tile=tile, zchunk=zc, stream=stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        b.step(steps, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1)
+        b.close()
+        out[f"batch_{prec}"] = {"updates_per_s": upd / (ms * 1e-3), "ms": ms, "wall_s": wall}
+        log(f"bench batched {prec}: {upd / (ms * 1e-3):.3e} updates/s")
+    runs = []
+    for i in insts:
+        p = ns.make_params(i["n"], reynolds=i["reynolds"], mach=i["mach"])
+        st = torch.empty((5, i["n"], i["n"], i["n"]), dtype=torch.float64, device="cuda")
+        wk = torch.empty(ns.ns_workspace_bytes(p, ns.NS_ALGO_FUSED, ns.NS_FP64),
+                         dtype=torch.uint8, device="cuda")
+        ns.tgv_init(p, st, stream)
+        runs.append((p, st, wk, i))
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for p, st, wk, i in runs:
+        ns.rk3_step(p, ns.NS_ALGO_FUSED, ns.NS_FP64, i["dt"], i["steps"], st, wk, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del runs
+    torch.cuda.empty_cache()
+    out["sequential_fp64"] = {"updates_per_s": upd / (ms * 1e-3), "ms": ms}
+    out["batch_fp32_over_sequential_fp64"] = (out["batch_fp32"]["updates_per_s"]
+                                              / out["sequential_fp64"]["updates_per_s"])
+    log(f"bench sequential fp64: {upd / (ms * 1e-3):.3e} updates/s")
+    return out
+
+
+def serving(tuner, seed=0, count=48, rate=50.0):
+    """Poisson arrivals (mean gap 1/rate s); N from {32,...,192}, Re, M as
+    above, steps ~ U{100..1000}.  The continuous-batching server in FP32
+    storage against sequential first-come-first-served FP64 solves."""
+    from paper_1709_09713_amd.serve import Server, serve_sequential
+    reqs = synth.poisson_requests(seed, count, rate_hz=rate)
+    for n in sorted({r["n"] for r in reqs}):
+        tuner.lookup(n, "fp32")
+    torch.cuda.synchronize()
+    srv = Server("fp32", max_instances=64, nstreams=4, quantum=25, tuner=tuner)
+    _, s32 = srv.run(reqs)
+    log(f"bench serving fp32: p50 {s32['p50_latency_s']:.2f} s p99 {s32['p99_latency_s']:.2f} s "
+        f"{s32['updates_per_s']:.3e} updates/s")
+    torch.cuda.empty_cache()
+    _, s64 = serve_sequential(reqs, "fp64")
+    log(f"bench serving sequential fp64: p50 {s64['p50_latency_s']:.2f} s "
+        f"p99 {s64['p99_latency_s']:.2f} s {s64['updates_per_s']:.3e} updates/s")
+    torch.cuda.empty_cache()
+    offered = sum(r["n"] ** 3 * 3 * r["steps"] for r in reqs) / (reqs[-1]["arrival"] or 1.0)
+    return {"requests": count, "seed": seed, "rate_hz": rate,
+            "offered_updates_per_s": offered, "hbm_budget_bytes": srv.hbm_budget,
+            "max_instances": srv.max_instances, "quantum_steps": srv.quantum,
+            "continuous_batching_fp32": s32, "sequential_fp64": s64,
+            "throughput_ratio": s32["updates_per_s"] / s64["updates_per_s"],
+            "error_bound_fp32_vs_fp64_oracle": 1e-5}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +191,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=list(ns.PRECS))
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "fused_fp64_256_traffic.json"))
     args = ap.parse_args()
 
@@ -162,6 +251,21 @@ def main():
         variants["fused_over_stored_512"] = f512 / s512
         variants["fused_over_stored_256"] = value / variants[f"stored_fp64_{n}"]["updates_per_s"]
 
+    batch_out = serve_out = None
+    if not (args.no_batched and args.no_serving):
+        from paper_1709_09713_amd.autotune import Autotuner
+        tuner = Autotuner()
+        if not args.no_batched:
+            log("bench: batched 64 instances")
+            batch_out = batched(tuner)
+        if not args.no_serving:
+            log(f"bench: serving {args.serve_requests} requests")
+            serve_out = serving(tuner, count=args.serve_requests)
+        tuned = {k: {"tile": v["tile"], "zchunk": v["zchunk"], "ms_per_step": v["ms_per_step"],
+                     "default_ms_per_step": v["default_ms_per_step"]}
+                 for k, v in tuner.table.items()}
+        (batch_out if batch_out is not None else serve_out)["autotuned"] = tuned
+
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
@@ -189,6 +293,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,
+        "batched": batch_out,
+        "serving": serve_out,
         "kinetic_energy_last_step": ke,
         "paper_context": "paper (other hardware, 256^3 TGV): best K40c SN2 ~1.14e8, 24-core Ivy "
                          "Bridge SN 4.58e7 updates/s (derived from its runtimes); "

@@ -163,6 +163,80 @@ ns_status ns_set_fused_config(int32_t tile, int32_t zchunk);
 ns_status ns_get_fused_config(const ns_params *p, ns_precision prec,
                               int32_t *tile, int32_t *zchunk);
 
+/* ------------------------------------------------------------------------
+ * Batched execution: many independent solves (different grid sizes,
+ * Reynolds and Mach numbers, time steps, step budgets) advanced together.
+ * Each member runs exactly the launches of rk3_step with the fused class
+ * (residual of the governing-equations section, RK3 of the time-advancement
+ * section) under its own launch shape; a batch step queues one RK3 step of
+ * every member with steps left, members spread over up to 4 internal HIP
+ * streams (balanced by grid points) that fork from and join back into the
+ * caller's stream, so small grids overlap on the device.  Per-point
+ * arithmetic never depends on the other members: a solve gives identical
+ * bits alone and in any mix.  Solves join (ns_batch_add) and leave
+ * (ns_batch_remove) between steps while the others keep their state.
+ * Ownership: the batch owns its streams, events and (with diagnostics) a
+ * device array of one ns_diag per slot; states and workspaces stay
+ * caller-owned, must outlive their membership, and may not be shared
+ * between members.  Calls on one batch are not thread-safe.
+ * ---------------------------------------------------------------------- */
+typedef struct ns_batch ns_batch;
+
+typedef struct {
+    ns_params p;        /* grid and physics of this solve */
+    double dt;          /* > 0, finite */
+    int32_t steps;      /* RK3 steps to run (>= 0) */
+    int32_t tile;       /* launch tile as in ns_set_fused_config, -1 = default */
+    int32_t zchunk;     /* z planes per block (>= 4), 0 = default */
+    double *state;      /* device, 5*N doubles: initial state in, result out */
+    void *work;         /* device, >= ns_workspace_bytes(p, NS_ALGO_FUSED, batch
+                           precision) bytes, 256-byte aligned */
+    size_t work_bytes;
+} ns_instance;
+
+/* Create a batch with room for max_instances (1..4096) solves advanced in
+ * precision prec over nstreams (1..4) internal streams; with_diagnostics
+ * != 0 computes each member's diagnostics of the state at the start of
+ * every step it runs (last one readable with ns_batch_poll).  Allocates
+ * streams, events and the diagnostics array (NS_ERR_DEVICE on failure);
+ * NS_ERR_ARG for bad arguments. */
+ns_status ns_batch_create(int32_t max_instances, ns_precision prec,
+                          int32_t nstreams, int32_t with_diagnostics,
+                          ns_batch **out);
+
+/* Wait for the batch's streams and free what the batch owns.  Caller
+ * buffers are untouched. */
+ns_status ns_batch_destroy(ns_batch *b);
+
+/* Admit a solve into a free slot (*slot).  It runs its `steps` steps during
+ * later ns_batch_step calls, in stream order after work queued before them
+ * on their stream (so a tgv_init queued there first is seen).  Host-side
+ * only.  NS_ERR_ARG / NS_ERR_SHAPE / NS_ERR_WORKSPACE as rk3_step for the
+ * instance, NS_ERR_ARG if its buffers overlap each other or another
+ * member's, NS_ERR_WORKSPACE if no slot is free. */
+ns_status ns_batch_add(ns_batch *b, const ns_instance *inst, int32_t *slot);
+
+/* Retire a slot (finished or not).  Host-side only: its state holds the
+ * last step queued, once the caller's stream of the last ns_batch_step has
+ * reached that point. */
+ns_status ns_batch_remove(ns_batch *b, int32_t slot);
+
+/* Queue nsteps RK3 steps of every member with steps left (a member stops at
+ * its own budget), ordered after earlier work on `stream`; later work on
+ * `stream` sees the results.  Asynchronous. */
+ns_status ns_batch_step(ns_batch *b, int32_t nsteps, void *stream);
+
+/* Fill host arrays of max_instances entries (any may be NULL) with each
+ * slot's steps left (-1 for a free slot) and steps queued so far; with
+ * diag non-NULL (batch created with diagnostics, else NS_ERR_ARG) copy the
+ * diagnostics array and synchronise `stream`. */
+ns_status ns_batch_poll(ns_batch *b, int32_t *steps_left, int32_t *steps_done,
+                        ns_diag *diag, void *stream);
+
+/* Capacity, occupied slots and internal stream count. */
+ns_status ns_batch_info(const ns_batch *b, int32_t *max_instances,
+                        int32_t *active, int32_t *nstreams);
+
 #ifdef __cplusplus
 }
 #endif

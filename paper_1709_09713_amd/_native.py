@@ -57,10 +57,18 @@ class ns_diag(ctypes.Structure):
 DIAG_NAMES = ("mass", "momentum_x", "momentum_y", "momentum_z", "energy",
               "kinetic_energy", "enstrophy", "dissipation")
 
+class ns_instance(ctypes.Structure):
+    _fields_ = [("p", ns_params), ("dt", ctypes.c_double), ("steps", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("zchunk", ctypes.c_int32), ("state", ctypes.c_void_p),
+                ("work", ctypes.c_void_p), ("work_bytes", ctypes.c_size_t)]
+
+
 # Exported C symbols, in header order.
 EXPORTS = ("ns_status_string", "ns_state_bytes", "ns_workspace_bytes",
            "tgv_init", "ns_residual", "rk3_step", "diagnostics",
-           "ns_set_fused_config", "ns_get_fused_config")
+           "ns_set_fused_config", "ns_get_fused_config",
+           "ns_batch_create", "ns_batch_destroy", "ns_batch_add", "ns_batch_remove",
+           "ns_batch_step", "ns_batch_poll", "ns_batch_info")
 
 
 class NativeError(RuntimeError):
@@ -103,6 +111,16 @@ def lib():
         L.ns_get_fused_config.restype = ctypes.c_int
         L.ns_get_fused_config.argtypes = [P, ctypes.c_int, ctypes.POINTER(i32),
                                           ctypes.POINTER(i32)]
+        pi32 = ctypes.POINTER(i32)
+        for f, args in (("ns_batch_create", [i32, ctypes.c_int, i32, i32, ctypes.POINTER(vp)]),
+                        ("ns_batch_destroy", [vp]),
+                        ("ns_batch_add", [vp, ctypes.POINTER(ns_instance), pi32]),
+                        ("ns_batch_remove", [vp, i32]),
+                        ("ns_batch_step", [vp, i32, vp]),
+                        ("ns_batch_poll", [vp, pi32, pi32, ctypes.POINTER(ns_diag), vp]),
+                        ("ns_batch_info", [vp, pi32, pi32, pi32])):
+            getattr(L, f).restype = ctypes.c_int
+            getattr(L, f).argtypes = args
         _lib = L
     return _lib
 
@@ -197,3 +215,54 @@ def ns_get_fused_config(p: ns_params, prec: int = NS_FP64):
     _check(lib().ns_get_fused_config(ctypes.byref(p), int(prec), ctypes.byref(t),
                                      ctypes.byref(z)), "ns_get_fused_config")
     return t.value, z.value
+
+
+# ---------------------------------------------------------------------------
+# Batched execution (ns_batch_*)
+
+def ns_batch_create(max_instances: int, prec: int, nstreams: int = 4,
+                    with_diagnostics: bool = False) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().ns_batch_create(int(max_instances), int(prec), int(nstreams),
+                                 1 if with_diagnostics else 0, ctypes.byref(h)), "ns_batch_create")
+    return h.value
+
+
+def ns_batch_destroy(handle: int):
+    _check(lib().ns_batch_destroy(handle), "ns_batch_destroy")
+
+
+def ns_batch_add(handle: int, p: ns_params, dt: float, steps: int, state, work,
+                 work_bytes: int = 0, tile: int = -1, zchunk: int = 0) -> int:
+    if work_bytes == 0 and not isinstance(work, int):
+        work_bytes = work.numel() * work.element_size()
+    inst = ns_instance(p, float(dt), int(steps), int(tile), int(zchunk), _ptr(state), _ptr(work),
+                       work_bytes)
+    slot = ctypes.c_int32()
+    _check(lib().ns_batch_add(handle, ctypes.byref(inst), ctypes.byref(slot)), "ns_batch_add")
+    return slot.value
+
+
+def ns_batch_remove(handle: int, slot: int):
+    _check(lib().ns_batch_remove(handle, int(slot)), "ns_batch_remove")
+
+
+def ns_batch_step(handle: int, nsteps: int, stream=None):
+    _check(lib().ns_batch_step(handle, int(nsteps), _stream(stream)), "ns_batch_step")
+
+
+def ns_batch_info(handle: int):
+    """(max_instances, active members, internal streams)."""
+    m, a, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().ns_batch_info(handle, ctypes.byref(m), ctypes.byref(a), ctypes.byref(s)),
+           "ns_batch_info")
+    return m.value, a.value, s.value
+
+
+def ns_batch_poll(handle: int, max_instances: int, with_diag: bool = False, stream=None):
+    """(steps_left list, steps_done list, diag list of dicts or None)."""
+    left = (ctypes.c_int32 * max_instances)()
+    done = (ctypes.c_int32 * max_instances)()
+    diag = (ns_diag * max_instances)() if with_diag else None
+    _check(lib().ns_batch_poll(handle, left, done, diag, _stream(stream)), "ns_batch_poll")
+    return (list(left), list(done), [d.as_dict() for d in diag] if with_diag else None)

@@ -37,20 +37,21 @@ Consts make_consts(const ns_params *p)
     return c;
 }
 
-// RK3 coefficients of the two-register low-storage scheme.
-static const double kRkA[3] = {2.0 / 3.0, 5.0 / 12.0, 3.0 / 5.0};
-static const double kRkB[3] = {1.0 / 4.0, 3.0 / 20.0, 3.0 / 5.0};
 
 constexpr int kMinZChunk = 4;
 static std::atomic<int> g_tile{-1};
 static std::atomic<int> g_zchunk{0};
 
-// Default launch shape.  The z march is unrolled by 5 over zchunk + 4
-// planes, so chunks of 5k + 1 planes carry no padding planes.
-static void choose_config(const Consts &c, ns_precision prec, int *tile, int *zchunk)
+// Launch shape: an explicit tile (>= 0) / zchunk (> 0) wins, else the
+// process-wide setting of ns_set_fused_config, else the default.  The z
+// march is unrolled by 5 over zchunk + 4 planes, so chunks of 5k + 1 planes
+// carry no padding planes.
+static void choose_config(const Consts &c, ns_precision prec, int tile_in, int zchunk_in, int *tile,
+                          int *zchunk)
 {
-    int t = g_tile.load();
-    int z = g_zchunk.load();
+    int t = tile_in >= 0 ? tile_in : g_tile.load();
+    int z = tile_in >= 0 ? zchunk_in : g_zchunk.load();
+    if (zchunk_in > 0) z = zchunk_in;
     if (t < 0 || t >= TILE_COUNT) t = (prec == NS_FP64) ? TILE_16x8 : TILE_32x8;
     if (z <= 0) {
         int bx, by;
@@ -66,6 +67,11 @@ static void choose_config(const Consts &c, ns_precision prec, int *tile, int *zc
     if (z > c.nz) z = c.nz;
     *tile = t;
     *zchunk = z;
+}
+
+static void choose_config(const Consts &c, ns_precision prec, int *tile, int *zchunk)
+{
+    choose_config(c, prec, -1, 0, tile, zchunk);
 }
 
 static int64_t max_partial_blocks(const Consts &c)
@@ -152,6 +158,73 @@ template <typename T>
 static T *at(void *work, size_t off)
 {
     return (T *)((char *)work + off);
+}
+
+ns_status make_fused_plan(const ns_params *p, ns_precision prec, int tile, int zchunk,
+                          double *state, void *work, size_t work_bytes, FusedPlan *out)
+{
+    ns_status st = check_params(p);
+    if (st != NS_OK) return st;
+    if (!valid_prec(prec) || !state || !out) return NS_ERR_ARG;
+    if (tile < -1 || tile >= TILE_COUNT || zchunk < 0 || (zchunk > 0 && zchunk < kMinZChunk))
+        return NS_ERR_ARG;
+    const Consts c = make_consts(p);
+    const Layout L = layout(c, NS_ALGO_FUSED, prec);
+    st = check_work(work, work_bytes, L.total);
+    if (st != NS_OK) return st;
+    FusedPlan f;
+    f.c = c;
+    f.prec = prec;
+    choose_config(c, prec, tile, zchunk, &f.tile, &f.zchunk);
+    f.nblk = fused_num_blocks(c, f.tile, f.zchunk);
+    f.state = state;
+    f.partial = at<double>(work, L.partial);
+    f.acc = at<double>(work, L.acc);
+    f.b1 = at<void>(work, L.b1);
+    f.b2 = at<void>(work, L.b2);
+    *out = f;
+    return NS_OK;
+}
+
+// One RK3 step of the fused class: stage 1 Q^n -> b1 (next stage input)
+// and the accumulator (plus the diagnostics partials of Q^n when diag_out
+// is given, reduced into *diag_out right after), stage 2 b1 -> b2 with the
+// accumulator in place, stage 3 b2 -> Q^{n+1} in the state buffer.
+hipError_t enqueue_fused_step(const FusedPlan &f, double dt, ns_diag *diag_out, hipStream_t s)
+{
+    StageArgs a = {};
+    a.zchunk = f.zchunk;
+    a.qin = f.state;
+    a.qout = f.b1;
+    a.acc_out = f.acc;
+    a.a_dt = rk_a(0) * dt;
+    a.b_dt = rk_b(0) * dt;
+    a.mode = 1;
+    a.diag_partial = diag_out ? f.partial : nullptr;
+    hipError_t e = launch_fused_stage(f.c, a, f.prec, f.tile, s);
+    if (e != hipSuccess) return e;
+    if (diag_out) {
+        e = launch_diag_finalize(f.c, f.partial, f.nblk, diag_out, s);
+        if (e != hipSuccess) return e;
+    }
+    a.qin = f.b1;
+    a.acc_in = f.acc;
+    a.acc_out = f.acc;
+    a.qout = f.b2;
+    a.a_dt = rk_a(1) * dt;
+    a.b_dt = rk_b(1) * dt;
+    a.mode = 2;
+    a.diag_partial = nullptr;
+    e = launch_fused_stage(f.c, a, f.prec, f.tile, s);
+    if (e != hipSuccess) return e;
+    a.qin = f.b2;
+    a.acc_in = f.acc;
+    a.acc_out = nullptr;
+    a.qout = f.state;
+    a.a_dt = rk_a(2) * dt;
+    a.b_dt = 0.0;
+    a.mode = 3;
+    return launch_fused_stage(f.c, a, f.prec, f.tile, s);
 }
 
 }  // namespace ns
@@ -268,42 +341,11 @@ ns_status rk3_step(const ns_params *p, ns_algo algo, ns_precision prec, double d
     void *b2 = at<void>(work, L.b2);
 
     if (algo == NS_ALGO_FUSED) {
-        int tile, zc;
-        choose_config(c, prec, &tile, &zc);
-        const int64_t nblk = fused_num_blocks(c, tile, zc);
-        for (int32_t step = 0; step < nsteps; ++step) {
-            StageArgs a = {};
-            a.zchunk = zc;
-            // stage 1: Q^n -> b1 (next stage input), acc
-            a.qin = state;
-            a.qout = b1;
-            a.acc_out = acc;
-            a.a_dt = kRkA[0] * dt;
-            a.b_dt = kRkB[0] * dt;
-            a.mode = 1;
-            a.diag_partial = diag_dev ? partial : nullptr;
-            NS_HIP_OK(launch_fused_stage(c, a, prec, tile, s));
-            if (diag_dev) NS_HIP_OK(launch_diag_finalize(c, partial, nblk, diag_dev + step, s));
-            // stage 2: b1 -> b2, acc in place
-            a.qin = b1;
-            a.acc_in = acc;
-            a.acc_out = acc;
-            a.qout = b2;
-            a.a_dt = kRkA[1] * dt;
-            a.b_dt = kRkB[1] * dt;
-            a.mode = 2;
-            a.diag_partial = nullptr;
-            NS_HIP_OK(launch_fused_stage(c, a, prec, tile, s));
-            // stage 3: b2 -> Q^{n+1} in state
-            a.qin = b2;
-            a.acc_in = acc;
-            a.acc_out = nullptr;
-            a.qout = state;
-            a.a_dt = kRkA[2] * dt;
-            a.b_dt = 0.0;
-            a.mode = 3;
-            NS_HIP_OK(launch_fused_stage(c, a, prec, tile, s));
-        }
+        FusedPlan f;
+        st = make_fused_plan(p, prec, -1, 0, state, work, work_bytes, &f);
+        if (st != NS_OK) return st;
+        for (int32_t step = 0; step < nsteps; ++step)
+            NS_HIP_OK(enqueue_fused_step(f, dt, diag_dev ? diag_dev + step : nullptr, s));
         return NS_OK;
     }
 
@@ -317,11 +359,11 @@ ns_status rk3_step(const ns_params *p, ns_algo algo, ns_precision prec, double d
             NS_HIP_OK(launch_diag_finalize(c, partial, diag_num_blocks(c), diag_dev + step, s));
         }
         NS_HIP_OK(stored_residual(c, state, R, wk, s));
-        NS_HIP_OK(launch_rk_update(c, R, state, acc, q1, kRkA[0] * dt, kRkB[0] * dt, s));
+        NS_HIP_OK(launch_rk_update(c, R, state, acc, q1, rk_a(0) * dt, rk_b(0) * dt, s));
         NS_HIP_OK(stored_residual(c, q1, R, wk, s));
-        NS_HIP_OK(launch_rk_update(c, R, acc, acc, q2, kRkA[1] * dt, kRkB[1] * dt, s));
+        NS_HIP_OK(launch_rk_update(c, R, acc, acc, q2, rk_a(1) * dt, rk_b(1) * dt, s));
         NS_HIP_OK(stored_residual(c, q2, R, wk, s));
-        NS_HIP_OK(launch_rk_update(c, R, acc, nullptr, state, kRkA[2] * dt, 0.0, s));
+        NS_HIP_OK(launch_rk_update(c, R, acc, nullptr, state, rk_a(2) * dt, 0.0, s));
     }
     return NS_OK;
 }

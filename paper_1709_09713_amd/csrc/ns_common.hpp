@@ -37,6 +37,18 @@ struct Consts {
 
 Consts make_consts(const ns_params *p);
 
+// Two-register low-storage RK3 (generic-algorithm figure): per stage k,
+// Q = Q_acc + a_k dt R and Q_acc += b_k dt R; a = (2/3, 5/12, 3/5),
+// b = (1/4, 3/20, 3/5).
+__host__ __device__ constexpr double rk_a(int k)
+{
+    return k == 0 ? 2.0 / 3.0 : (k == 1 ? 5.0 / 12.0 : 3.0 / 5.0);
+}
+__host__ __device__ constexpr double rk_b(int k)
+{
+    return k == 0 ? 1.0 / 4.0 : (k == 1 ? 3.0 / 20.0 : 3.0 / 5.0);
+}
+
 __host__ __device__ inline int wrap1(int i, int n)
 {
     // single wrap: valid for -n <= i < 2n

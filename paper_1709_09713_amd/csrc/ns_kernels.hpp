@@ -30,6 +30,23 @@ int64_t fused_num_blocks(const Consts &c, int tile, int zchunk);
 hipError_t launch_fused_stage(const Consts &c, const StageArgs &s, ns_precision prec,
                               int tile, hipStream_t st);
 
+// A validated fused-class RK3 plan for one solve: constants, launch shape
+// and the carve-up of its workspace.  rk3_step and the batch scheduler
+// enqueue steps through it, so both run the same launches.
+struct FusedPlan {
+    Consts c;
+    ns_precision prec;
+    int tile, zchunk;
+    int64_t nblk;
+    double *state, *partial, *acc;
+    void *b1, *b2;
+};
+// tile -1 / zchunk 0 take the process-wide or default launch shape.
+// Validates everything (params, precision, shape, workspace) first.
+ns_status make_fused_plan(const ns_params *p, ns_precision prec, int tile, int zchunk,
+                          double *state, void *work, size_t work_bytes, FusedPlan *out);
+hipError_t enqueue_fused_step(const FusedPlan &f, double dt, ns_diag *diag_out, hipStream_t s);
+
 // Diagnostics: per-block partial sums of a state, then a one-block fixed-order
 // final reduction into an ns_diag record.
 int64_t diag_num_blocks(const Consts &c);

@@ -148,3 +148,35 @@ def test_package_has_no_cpu_fallback():
         if fn.endswith(".py"):
             src = open(os.path.join(pkg, fn)).read()
             assert "oracle" not in src, fn
+
+
+def test_batch_create_validates_before_touching_the_device():
+    # (max_instances, precision, nstreams, with_diagnostics)
+    for args in ((0, 0, 1, 0), (4097, 0, 1, 0), (4, 5, 1, 0), (4, 0, 0, 0), (4, 0, 5, 0)):
+        with pytest.raises(ns.NativeError) as e:
+            ns.ns_batch_create(*args)
+        assert e.value.status == ns.NS_ERR_ARG
+
+
+def test_batch_calls_reject_null_handle():
+    import ctypes
+    L = ns.lib()
+    assert L.ns_batch_step(None, 1, None) == ns.NS_ERR_ARG
+    assert L.ns_batch_remove(None, 0) == ns.NS_ERR_ARG
+    assert L.ns_batch_destroy(None) == ns.NS_ERR_ARG
+    assert L.ns_batch_poll(None, None, None, None, None) == ns.NS_ERR_ARG
+    assert L.ns_batch_info(None, None, None, None) == ns.NS_ERR_ARG
+    slot = ctypes.c_int32()
+    assert L.ns_batch_add(None, None, ctypes.byref(slot)) == ns.NS_ERR_ARG
+    assert L.ns_batch_create(1, 0, 1, 0, None) == ns.NS_ERR_ARG
+
+
+def test_instance_struct_matches_header():
+    """ns_instance field order and offsets agree between the header and the
+    ctypes binding (the struct crosses the ABI by pointer)."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\} ns_instance;", text).group(1)
+    names = re.findall(r"(\w+)\s*;", body)
+    assert tuple(names) == tuple(f for f, _ in nat.ns_instance._fields_)
+    assert nat.ns_instance.tile.offset == nat.ns_instance.steps.offset + 4
+    assert nat.ns_instance.state.offset % 8 == 0

@@ -167,6 +167,33 @@ def test_tilings_match_oracle_and_zchunk_is_bitwise(ns):
         ns.ns_set_fused_config(-1, 0)
 
 
+def test_fp32_tilings_match_oracle_and_zchunk_is_bitwise(ns):
+    """FP32 storage under every launch shape (the autotuner may pick any):
+    within the FP32 bound of the oracle, and bit-identical across z-chunk
+    lengths for each tile shape (different tile shapes are separate
+    instantiations whose instruction selection may differ in rounding)."""
+    n = (37, 21, 19)
+    ph = phys(n, mach=0.2)
+    p = params(ns, n, mach=0.2)
+    Q0 = oracle.tgv_init(ph)
+    want = oracle.rk3(ph, Q0, 1e-3, 3)
+    try:
+        for tile in ns.TILES:
+            ref = None
+            for zc in (4, 11):
+                print(f"fp32 tile {tile} zchunk {zc}", flush=True)
+                ns.ns_set_fused_config(tile, zc)
+                got = gpu_rk3(ns, p, ns.NS_ALGO_FUSED, ns.NS_FP32_STORE, Q0, 1e-3, 3)
+                e = max(rel(got, want))
+                assert 1e-12 < e < 1e-5, (tile, zc, e)
+                if ref is None:
+                    ref = got
+                else:
+                    assert np.array_equal(got, ref), (tile, zc)
+    finally:
+        ns.ns_set_fused_config(-1, 0)
+
+
 def test_diagnostics_standalone(ns):
     n = (24, 20, 18)
     Q = synth.random_state(n[::-1], seed=5)
