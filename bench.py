@@ -20,6 +20,7 @@ server, p50/p99 latency and throughput, against sequential FP64 solves).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -40,6 +41,19 @@ HBM_PEAK_GBS = 8000.0
 # writes the next stage input and the accumulator (120 B), stage 2 reads two
 # and writes two (160 B), stage 3 reads two and writes the state (120 B).
 BYTES_PER_POINT_STEP = {"fp64": 400.0, "fp32": 320.0}
+
+
+# Sources of the fused stage kernel: traffic counters recorded for another
+# version of them are not reported.
+FUSED_SOURCES = ("paper_1709_09713_amd/csrc/ns_fused.hip", "paper_1709_09713_amd/csrc/ns_common.hpp")
+
+
+def fused_source_hash():
+    h = hashlib.sha256()
+    for rel in FUSED_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def log(msg):
@@ -229,7 +243,8 @@ def main():
         if os.path.exists(args.traffic_json):
             with open(args.traffic_json) as f:
                 t = json.load(f)
-            if t.get("n") == n and t.get("precision") == args.precision:
+            if (t.get("n") == n and t.get("precision") == args.precision
+                    and t.get("source_sha256") == fused_source_hash()):
                 traffic = t.get("bytes_per_launch")
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
