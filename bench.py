@@ -11,11 +11,14 @@ run on, bracketed by device synchronisation.
 Prints one JSON line.  Extra keys: ``roofline`` (dominant kernel: the fused
 stage kernel), ``cpu_baseline`` (the FP64 oracle on the host cores, one RK3
 step of the same workload), ``variants`` (stored-derivative class,
-FP32 storage, and the 512^3 fused-vs-stored comparison), ``batched`` (64
+FP32 storage, the intermediate-storage class, and the 512^3 comparison of
+the three classes), ``batched`` (64
 independent TGV instances of mixed sizes, FP32 storage, autotuned launch
 shapes, against the same instances solved one after another in FP64) and
 ``serving`` (a Poisson request stream through the continuous-batching
-server, p50/p99 latency and throughput, against sequential FP64 solves).
+server, p50/p99 latency and throughput, against sequential FP64 solves) and
+``energy`` (energy to solution per step and per update of the fused and
+stored classes, from the board energy counter).
 """
 from __future__ import annotations
 
@@ -168,6 +171,35 @@ def batched(tuner, seed=0, count=64, steps=200):
     return out
 
 
+def energy(n):
+    """Energy to solution of the fused and stored FP64 classes (and FP32
+    storage) on the n^3 TGV: the board energy counter around a run of
+    at least 2.5 seconds per variant."""
+    from paper_1709_09713_amd.energy import EnergyMeter
+    meter = EnergyMeter()
+    if not meter.available:
+        return {"available": False, "reason": meter.reason}
+    out = {"available": True, "method": "AMD SMI current socket power sampled every ~10 ms, "
+           "trapezoid integral over >= 2.5 s of back-to-back steps; counter_watts = the board "
+           "energy counter's mean power over its whole update intervals inside the run",
+           "n": n}
+    for algo, prec, k in (("fused", "fp64", 100), ("fused", "fp32", 100), ("some", "fp64", 20),
+                          ("stored", "fp64", 10)):
+        r = Run(n, algo, prec)
+        r.steps(2)
+        m = meter.measure(lambda: r.steps(k), min_seconds=2.5)
+        r.free()
+        steps = k * m["calls"]
+        upd = n ** 3 * 3 * steps
+        out[f"{algo}_{prec}"] = dict(m, steps=steps, joules_per_step=m["joules"] / steps,
+                                     nanojoules_per_update=m["joules"] / upd * 1e9,
+                                     updates_per_s=upd / m["seconds"])
+        log(f"bench energy {algo} {prec}: {m['joules'] / steps:.3f} J/step, {m['mean_watts']:.0f} W")
+    out["stored_over_fused_energy_fp64"] = (out["stored_fp64"]["joules_per_step"]
+                                            / out["fused_fp64"]["joules_per_step"])
+    return out
+
+
 def serving(tuner, seed=0, count=48, rate=50.0):
     """Poisson arrivals (mean gap 1/rate s); N from {32,...,192}, Re, M as
     above, steps ~ U{100..1000}.  The continuous-batching server in FP32
@@ -207,6 +239,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-energy", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "fused_fp64_256_traffic.json"))
     args = ap.parse_args()
@@ -253,8 +286,9 @@ def main():
 
     variants = {}
     if not args.no_variants:
-        for (vn, va, vp, vk) in ((n, "stored", "fp64", 10), (n, "fused", "fp32", K),
-                                 (512, "fused", "fp64", 10), (512, "stored", "fp64", 3)):
+        for (vn, va, vp, vk) in ((n, "stored", "fp64", 10), (n, "some", "fp64", 20),
+                                 (n, "fused", "fp32", K), (512, "fused", "fp64", 10),
+                                 (512, "stored", "fp64", 3), (512, "some", "fp64", 5)):
             log(f"bench variant: {vn}^3 {va} {vp} x{vk}")
             r = Run(vn, va, vp)
             vms, _, _ = r.time_steps(vk, 2)
@@ -265,6 +299,7 @@ def main():
         s512 = variants["stored_fp64_512"]["updates_per_s"]
         variants["fused_over_stored_512"] = f512 / s512
         variants["fused_over_stored_256"] = value / variants[f"stored_fp64_{n}"]["updates_per_s"]
+        variants["fused_over_some_512"] = f512 / variants["some_fp64_512"]["updates_per_s"]
 
     batch_out = serve_out = None
     if not (args.no_batched and args.no_serving):
@@ -280,6 +315,11 @@ def main():
                      "default_ms_per_step": v["default_ms_per_step"]}
                  for k, v in tuner.table.items()}
         (batch_out if batch_out is not None else serve_out)["autotuned"] = tuned
+
+    energy_out = None
+    if not args.no_energy:
+        log("bench: energy to solution")
+        energy_out = energy(n)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -310,6 +350,7 @@ def main():
         "variants": variants,
         "batched": batch_out,
         "serving": serve_out,
+        "energy": energy_out,
         "kinetic_energy_last_step": ke,
         "paper_context": "paper (other hardware, 256^3 TGV): best K40c SN2 ~1.14e8, 24-core Ivy "
                          "Bridge SN 4.58e7 updates/s (derived from its runtimes); "

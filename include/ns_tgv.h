@@ -48,17 +48,22 @@ typedef enum {
     NS_ERR_WORKSPACE = -3,   /* work_bytes smaller than ns_workspace_bytes() or misaligned */
     NS_ERR_DEVICE = -4,      /* a HIP call failed */
     NS_ERR_NONFINITE = -5,   /* diagnostics found a NaN or infinity */
-    NS_ERR_UNSUPPORTED = -7  /* valid but not provided (stored class in FP32 storage) */
+    NS_ERR_UNSUPPORTED = -7  /* valid but not provided (stored or intermediate-storage
+                                class in FP32 storage) */
 } ns_status;
 
-/* The two algorithm classes compared in the algorithms section.
+/* The algorithm classes compared in the algorithms section.
  * NS_ALGO_STORED: every derivative is written to its own global array and
  *   the residual is assembled from those arrays (the baseline algorithm,
  *   BL).
  * NS_ALGO_FUSED: no derivative array; derivatives are evaluated on the fly
  *   from LDS-staged tiles and accumulated straight into the residual (the
- *   minimal-storage class RA / SN / SN2). */
-typedef enum { NS_ALGO_STORED = 0, NS_ALGO_FUSED = 1 } ns_algo;
+ *   minimal-storage class RA / SN / SN2).
+ * NS_ALGO_SOME: intermediate storage (RS / SS): only the nine
+ *   velocity-gradient components du_i/dx_j are stored in global arrays each
+ *   stage; every other derivative is evaluated inline, and the mixed
+ *   viscous derivatives are first derivatives of the stored gradients. */
+typedef enum { NS_ALGO_STORED = 0, NS_ALGO_FUSED = 1, NS_ALGO_SOME = 2 } ns_algo;
 
 /* NS_FP64: all storage and arithmetic in double.
  * NS_FP32_STORE: the Runge-Kutta stage inputs are stored and differenced in
@@ -131,8 +136,9 @@ ns_status ns_residual(const ns_params *p, ns_algo algo, const double *Q,
  * nsteps >= 0.  If diag_dev is not NULL it is a device array of nsteps
  * ns_diag records: record s receives the diagnostics of the state at the
  * start of step s (computed inside the first stage).  work needs
- * ns_workspace_bytes(p, algo, prec) bytes.  algo = NS_ALGO_STORED requires
- * prec = NS_FP64 (else NS_ERR_UNSUPPORTED). */
+ * ns_workspace_bytes(p, algo, prec) bytes.  algo = NS_ALGO_STORED and
+ * NS_ALGO_SOME require prec = NS_FP64 (else NS_ERR_UNSUPPORTED); their
+ * per-step diagnostics take one extra pass over the state. */
 ns_status rk3_step(const ns_params *p, ns_algo algo, ns_precision prec,
                    double dt, int32_t nsteps, double *state, void *work,
                    size_t work_bytes, ns_diag *diag_dev, void *stream);

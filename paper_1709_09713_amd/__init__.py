@@ -5,7 +5,7 @@ marshalling only) plus ``Solver``, a convenience holder of one state and
 its workspace in device memory.  The hot path runs entirely in the HIP
 kernels of ``libns_tgv.so``; there is no CPU fallback.
 """
-from ._native import (ALGOS, DIAG_NAMES, EXPORTS, NS_ALGO_FUSED, NS_ALGO_STORED,  # noqa: F401
+from ._native import (ALGOS, DIAG_NAMES, EXPORTS, NS_ALGO_FUSED, NS_ALGO_SOME, NS_ALGO_STORED,  # noqa: F401
                       NS_ERR_ARG, NS_ERR_DEVICE, NS_ERR_NONFINITE, NS_ERR_SHAPE,
                       NS_ERR_UNSUPPORTED, NS_ERR_WORKSPACE, NS_FP32_STORE, NS_FP64, NS_OK,
                       PRECS, TILES, NativeError, diagnostics, lib, make_params,

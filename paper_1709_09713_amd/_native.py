@@ -26,10 +26,11 @@ NS_ERR_UNSUPPORTED = -7
 
 NS_ALGO_STORED = 0
 NS_ALGO_FUSED = 1
+NS_ALGO_SOME = 2
 NS_FP64 = 0
 NS_FP32_STORE = 1
 
-ALGOS = {"stored": NS_ALGO_STORED, "fused": NS_ALGO_FUSED}
+ALGOS = {"stored": NS_ALGO_STORED, "fused": NS_ALGO_FUSED, "some": NS_ALGO_SOME}
 PRECS = {"fp64": NS_FP64, "fp32": NS_FP32_STORE}
 
 TILES = {0: (32, 8), 1: (16, 16), 2: (64, 4), 3: (32, 16), 4: (16, 8), 5: (32, 4),

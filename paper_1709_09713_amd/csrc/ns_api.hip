@@ -87,7 +87,7 @@ static int64_t max_partial_blocks(const Consts &c)
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t partial, rec, acc, b1, b2, R, stored, total;
+    size_t partial, rec, acc, b1, b2, R, stored, G, total;
 };
 
 // Scratch layout.  The diagnostic partials and one ns_diag record come
@@ -109,7 +109,11 @@ static Layout layout(const Consts &c, ns_algo algo, ns_precision prec)
     off = align256(off + n5 * stage_elt);
     L.b2 = off;
     off = align256(off + n5 * stage_elt);
-    L.R = L.stored = 0;
+    L.R = L.stored = L.G = 0;
+    if (algo == NS_ALGO_SOME) {
+        L.G = off;
+        off = align256(off + rs_workspace_doubles(c) * sizeof(double));
+    }
     if (algo == NS_ALGO_STORED) {
         L.R = off;
         off = align256(off + n5 * sizeof(double));
@@ -143,7 +147,7 @@ static ns_status check_params(const ns_params *p)
     return NS_OK;
 }
 
-static bool valid_algo(int a) { return a == NS_ALGO_STORED || a == NS_ALGO_FUSED; }
+static bool valid_algo(int a) { return a == NS_ALGO_STORED || a == NS_ALGO_FUSED || a == NS_ALGO_SOME; }
 static bool valid_prec(int q) { return q == NS_FP64 || q == NS_FP32_STORE; }
 
 static ns_status check_work(const void *work, size_t have, size_t need)
@@ -256,7 +260,7 @@ size_t ns_state_bytes(const ns_params *p)
 size_t ns_workspace_bytes(const ns_params *p, ns_algo algo, ns_precision prec)
 {
     if (check_params(p) != NS_OK || !valid_algo(algo) || !valid_prec(prec)) return 0;
-    if (algo == NS_ALGO_STORED && prec != NS_FP64) return 0;
+    if (algo != NS_ALGO_FUSED && prec != NS_FP64) return 0;
     return layout(make_consts(p), algo, prec).total;
 }
 
@@ -317,6 +321,10 @@ ns_status ns_residual(const ns_params *p, ns_algo algo, const double *Q, double 
     const Layout L = layout(c, algo, NS_FP64);
     st = check_work(work, work_bytes, L.total);
     if (st != NS_OK) return st;
+    if (algo == NS_ALGO_SOME) {
+        NS_HIP_OK(rs_stage(c, Q, at<double>(work, L.G), nullptr, nullptr, nullptr, R, 0.0, 0.0, 0, s));
+        return NS_OK;
+    }
     NS_HIP_OK(stored_residual(c, Q, R, at<double>(work, L.stored), s));
     return NS_OK;
 }
@@ -328,7 +336,7 @@ ns_status rk3_step(const ns_params *p, ns_algo algo, ns_precision prec, double d
     if (st != NS_OK) return st;
     if (!valid_algo(algo) || !valid_prec(prec) || !state) return NS_ERR_ARG;
     if (!std::isfinite(dt) || !(dt > 0.0) || nsteps < 0) return NS_ERR_ARG;
-    if (algo == NS_ALGO_STORED && prec != NS_FP64) return NS_ERR_UNSUPPORTED;
+    if (algo != NS_ALGO_FUSED && prec != NS_FP64) return NS_ERR_UNSUPPORTED;
     const Consts c = make_consts(p);
     const Layout L = layout(c, algo, prec);
     st = check_work(work, work_bytes, L.total);
@@ -346,6 +354,21 @@ ns_status rk3_step(const ns_params *p, ns_algo algo, ns_precision prec, double d
         if (st != NS_OK) return st;
         for (int32_t step = 0; step < nsteps; ++step)
             NS_HIP_OK(enqueue_fused_step(f, dt, diag_dev ? diag_dev + step : nullptr, s));
+        return NS_OK;
+    }
+
+    if (algo == NS_ALGO_SOME) {
+        double *G = at<double>(work, L.G);
+        double *q1 = (double *)b1, *q2 = (double *)b2;
+        for (int32_t step = 0; step < nsteps; ++step) {
+            if (diag_dev) {
+                NS_HIP_OK(launch_diag_partials(c, state, partial, s));
+                NS_HIP_OK(launch_diag_finalize(c, partial, diag_num_blocks(c), diag_dev + step, s));
+            }
+            NS_HIP_OK(rs_stage(c, state, G, nullptr, acc, q1, nullptr, rk_a(0) * dt, rk_b(0) * dt, 1, s));
+            NS_HIP_OK(rs_stage(c, q1, G, acc, acc, q2, nullptr, rk_a(1) * dt, rk_b(1) * dt, 2, s));
+            NS_HIP_OK(rs_stage(c, q2, G, acc, nullptr, state, nullptr, rk_a(2) * dt, 0.0, 3, s));
+        }
         return NS_OK;
     }
 

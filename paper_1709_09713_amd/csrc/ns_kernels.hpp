@@ -60,6 +60,12 @@ hipError_t launch_tgv_init(const Consts &c, const ns_params *p, double *state, h
 
 // Stored-derivative (baseline) class.
 size_t stored_workspace_doubles(const Consts &c);
+// Intermediate-storage class: nine gradient arrays; one stage = gradient
+// sweep + residual/RK sweep (mode 0 writes R to rout).
+size_t rs_workspace_doubles(const Consts &c);
+hipError_t rs_stage(const Consts &c, const double *qin, double *G, const double *acc_in,
+                    double *acc_out, double *qout, double *rout, double a_dt, double b_dt,
+                    int mode, hipStream_t st);
 hipError_t stored_residual(const Consts &c, const double *Q, double *R, double *work,
                            hipStream_t st);
 hipError_t launch_rk_update(const Consts &c, const double *R, const double *acc_in,

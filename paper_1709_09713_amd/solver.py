@@ -10,7 +10,8 @@ from . import _native as nat
 class Solver:
     """A periodic TGV solve on the current CUDA (HIP) device.
 
-    algo: "fused" or "stored"; precision: "fp64" or "fp32" (FP32 storage of
+    algo: "fused", "stored" or "some" (intermediate storage: nine
+    velocity-gradient arrays); precision: "fp64" or "fp32" (FP32 storage of
     the stage inputs, fused class only).
     """
 

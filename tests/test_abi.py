@@ -52,6 +52,9 @@ def test_sizes():
     assert 5 * 16 ** 3 * 16 <= w32 < wf        # float stage buffers
     assert ws >= wf + 85 * 16 ** 3 * 8         # residual + 80 work arrays
     assert ns.ns_workspace_bytes(p, ns.NS_ALGO_STORED, ns.NS_FP32_STORE) == 0
+    wr = ns.ns_workspace_bytes(p, ns.NS_ALGO_SOME, ns.NS_FP64)
+    assert wr >= wf + 9 * 16 ** 3 * 8 and wr < ws   # nine gradient arrays
+    assert ns.ns_workspace_bytes(p, ns.NS_ALGO_SOME, ns.NS_FP32_STORE) == 0
     assert ns.ns_workspace_bytes(p, 7, ns.NS_FP64) == 0
     p2 = ns.make_params((5, 6, 7))
     assert ns.ns_state_bytes(p2) == 5 * 5 * 6 * 7 * 8
@@ -104,6 +107,8 @@ def test_rk3_argument_checks():
         (dict(work_bytes=wb - 1), ns.NS_ERR_WORKSPACE),
         (dict(work=0x1010), ns.NS_ERR_WORKSPACE),          # misaligned
         (dict(algo=ns.NS_ALGO_STORED, prec=ns.NS_FP32_STORE), ns.NS_ERR_UNSUPPORTED),
+        (dict(algo=ns.NS_ALGO_SOME, prec=ns.NS_FP32_STORE), ns.NS_ERR_UNSUPPORTED),
+        (dict(algo=3), ns.NS_ERR_ARG),
         (dict(prec=5), ns.NS_ERR_ARG),
     ]
     for over, code in cases:

@@ -100,7 +100,7 @@ def test_tgv_init(ns, n):
 SHAPES = [(16, 16, 16), (24, 20, 18), (37, 11, 9), (5, 5, 5), (40, 36, 28), (64, 64, 64)]
 
 
-@pytest.mark.parametrize("algo", ["fused", "stored"])
+@pytest.mark.parametrize("algo", ["fused", "stored", "some"])
 @pytest.mark.parametrize("n", SHAPES)
 def test_residual_random_state(ns, algo, n):
     Q = synth.random_state(n[::-1], seed=n[0] * 7 + n[1])
@@ -114,7 +114,7 @@ def test_residual_random_state(ns, algo, n):
         assert max(e) < tol_residual(n), e
 
 
-@pytest.mark.parametrize("algo", ["fused", "stored"])
+@pytest.mark.parametrize("algo", ["fused", "stored", "some"])
 def test_rk3_tgv_16_ten_steps(ns, algo):
     """16^3 Taylor-Green vortex, dt = 3.385e-3, 10 steps, FP64."""
     n = (16, 16, 16)
@@ -127,7 +127,7 @@ def test_rk3_tgv_16_ten_steps(ns, algo):
     assert max(e) < TOL, e
 
 
-@pytest.mark.parametrize("algo", ["fused", "stored"])
+@pytest.mark.parametrize("algo", ["fused", "stored", "some"])
 def test_rk3_ragged_random(ns, algo):
     n = (40, 36, 28)
     Q0 = synth.random_state(n[::-1], seed=11)
@@ -207,7 +207,8 @@ def test_diagnostics_standalone(ns):
         assert abs(d[k] - want[k]) <= 1e-12 * scale + 1e-13, (k, d[k], want[k])
 
 
-@pytest.mark.parametrize("algo,prec", [("fused", "fp64"), ("stored", "fp64"), ("fused", "fp32")])
+@pytest.mark.parametrize("algo,prec", [("fused", "fp64"), ("stored", "fp64"), ("some", "fp64"),
+                                       ("fused", "fp32")])
 def test_per_step_diagnostics(ns, algo, prec):
     """rk3_step's per-step records equal the oracle diagnostics of the state
     at the start of each step."""
@@ -292,7 +293,7 @@ def _sampled_check(ns, n, algo, steps, npts):
     return Q
 
 
-@pytest.mark.parametrize("algo", ["fused", "stored"])
+@pytest.mark.parametrize("algo", ["fused", "stored", "some"])
 def test_256_sampled_residual(ns, algo):
     _sampled_check(ns, (256, 256, 256), algo, 3, 3000)
 
@@ -302,13 +303,13 @@ def test_512_sampled_residual_fused(ns):
 
 
 def test_256_fused_vs_stored_states_and_conservation(ns):
-    """256^3 TGV, 20 steps: the two GPU classes agree element by element and
-    mass / momentum are conserved to rounding."""
+    """256^3 TGV, 20 steps: the three GPU classes agree element by element
+    and mass / momentum are conserved to rounding."""
     n = (256, 256, 256)
     p = params(ns, n)
     dt = synth.stable_dt(256, 0.1)
     out = {}
-    for algo in ("fused", "stored"):
+    for algo in ("fused", "stored", "some"):
         Qd = torch.empty((5, 256, 256, 256), dtype=torch.float64, device="cuda")
         ns.tgv_init(p, Qd)
         s0 = Qd.sum(dim=(1, 2, 3)).cpu().numpy()
@@ -316,11 +317,18 @@ def test_256_fused_vs_stored_states_and_conservation(ns):
         torch.cuda.synchronize()
         s1 = Qd.sum(dim=(1, 2, 3)).cpu().numpy()
         assert abs(s1[0] - s0[0]) < 1e-12 * abs(s0[0])
+        # Sum rho u_i = 0 up to rounding: each of the 3 x 20 stage updates
+        # rounds every point by at most eps |m|, and the device sum itself
+        # by about log2(N) eps sum|m|.
+        eps = np.finfo(np.float64).eps / 2
+        absm = Qd[1:4].abs().sum(dim=(1, 2, 3)).cpu().numpy()
         for v in (1, 2, 3):
-            assert abs(s1[v] - s0[v]) < 1e-9
+            bound = (3 * 20 + 2 * np.log2(Qd[0].numel())) * eps * absm[v - 1]
+            assert abs(s1[v] - s0[v]) < bound, (algo, v, s1[v] - s0[v], bound)
         out[algo] = Qd.cpu().numpy()
         del Qd
         torch.cuda.empty_cache()
-    e = rel(out["fused"], out["stored"])
-    print(f"256^3x20 fused vs stored: rel={max(e):.2e}", flush=True)
-    assert max(e) < TOL, e
+    for other in ("stored", "some"):
+        e = rel(out["fused"], out[other])
+        print(f"256^3x20 fused vs {other}: rel={max(e):.2e}", flush=True)
+        assert max(e) < TOL, (other, e)
