@@ -295,6 +295,22 @@ def main():
             r.free()
             variants[f"{va}_{vp}_{vn}"] = {"updates_per_s": vn ** 3 * 3 * vk / (vms * 1e-3),
                                           "ms_per_step": vms / vk, "steps": vk}
+        # evaluation-order study: the same kernels with the in-plane terms
+        # grouped by derivative direction instead of by equation
+        for vp, tile in (("fp64", 4), ("fp32", 0)):
+            ns.ns_set_fused_config(tile, 0)
+            ns.ns_set_fused_order(1)
+            try:
+                log(f"bench variant: {n}^3 fused {vp} by-direction order")
+                r = Run(n, "fused", vp)
+                vms, _, _ = r.time_steps(K, 2)
+                r.free()
+            finally:
+                ns.ns_set_fused_order(0)
+                ns.ns_set_fused_config(-1, 0)
+            variants[f"fused_{vp}_{n}_order_by_direction"] = {
+                "updates_per_s": n ** 3 * 3 * K / (vms * 1e-3), "ms_per_step": vms / K, "steps": K,
+                "tile": tile}
         f512 = variants["fused_fp64_512"]["updates_per_s"]
         s512 = variants["stored_fp64_512"]["updates_per_s"]
         variants["fused_over_stored_512"] = f512 / s512

@@ -169,6 +169,20 @@ ns_status ns_set_fused_config(int32_t tile, int32_t zchunk);
 ns_status ns_get_fused_config(const ns_params *p, ns_precision prec,
                               int32_t *tile, int32_t *zchunk);
 
+/* Evaluation order of the fused kernel's in-plane residual terms,
+ * process-wide (the SN / SN2 distinction of the minimal-storage section):
+ * 0 = grouped by equation, the momentum equations by velocity component
+ * (default); 1 = grouped by derivative direction (all x derivatives of all
+ * equations, then all y derivatives).  The two orders sum the same terms
+ * with a different association, so results differ at the rounding level
+ * only.  Order 1 is compiled for tiles 16x8 and 32x8 only: rk3_step,
+ * ns_residual and ns_batch_add return NS_ERR_UNSUPPORTED for it with any
+ * other tile.  NS_ERR_ARG for other values. */
+ns_status ns_set_fused_order(int32_t order);
+
+/* The current evaluation order (0 or 1). */
+int32_t ns_get_fused_order(void);
+
 /* ------------------------------------------------------------------------
  * Batched execution: many independent solves (different grid sizes,
  * Reynolds and Mach numbers, time steps, step budgets) advanced together.

@@ -67,7 +67,8 @@ class ns_instance(ctypes.Structure):
 # Exported C symbols, in header order.
 EXPORTS = ("ns_status_string", "ns_state_bytes", "ns_workspace_bytes",
            "tgv_init", "ns_residual", "rk3_step", "diagnostics",
-           "ns_set_fused_config", "ns_get_fused_config",
+           "ns_set_fused_config", "ns_get_fused_config", "ns_set_fused_order",
+           "ns_get_fused_order",
            "ns_batch_create", "ns_batch_destroy", "ns_batch_add", "ns_batch_remove",
            "ns_batch_step", "ns_batch_poll", "ns_batch_info")
 
@@ -112,6 +113,10 @@ def lib():
         L.ns_get_fused_config.restype = ctypes.c_int
         L.ns_get_fused_config.argtypes = [P, ctypes.c_int, ctypes.POINTER(i32),
                                           ctypes.POINTER(i32)]
+        L.ns_set_fused_order.restype = ctypes.c_int
+        L.ns_set_fused_order.argtypes = [i32]
+        L.ns_get_fused_order.restype = i32
+        L.ns_get_fused_order.argtypes = []
         pi32 = ctypes.POINTER(i32)
         for f, args in (("ns_batch_create", [i32, ctypes.c_int, i32, i32, ctypes.POINTER(vp)]),
                         ("ns_batch_destroy", [vp]),
@@ -216,6 +221,14 @@ def ns_get_fused_config(p: ns_params, prec: int = NS_FP64):
     _check(lib().ns_get_fused_config(ctypes.byref(p), int(prec), ctypes.byref(t),
                                      ctypes.byref(z)), "ns_get_fused_config")
     return t.value, z.value
+
+
+def ns_set_fused_order(order: int):
+    _check(lib().ns_set_fused_order(int(order)), "ns_set_fused_order")
+
+
+def ns_get_fused_order() -> int:
+    return int(lib().ns_get_fused_order())
 
 
 # ---------------------------------------------------------------------------

@@ -41,6 +41,7 @@ Consts make_consts(const ns_params *p)
 constexpr int kMinZChunk = 4;
 static std::atomic<int> g_tile{-1};
 static std::atomic<int> g_zchunk{0};
+static std::atomic<int> g_order{0};
 
 // Launch shape: an explicit tile (>= 0) / zchunk (> 0) wins, else the
 // process-wide setting of ns_set_fused_config, else the default.  The z
@@ -180,6 +181,8 @@ ns_status make_fused_plan(const ns_params *p, ns_precision prec, int tile, int z
     f.c = c;
     f.prec = prec;
     choose_config(c, prec, tile, zchunk, &f.tile, &f.zchunk);
+    f.order = g_order.load();
+    if (!fused_order_supported(f.tile, f.order)) return NS_ERR_UNSUPPORTED;
     f.nblk = fused_num_blocks(c, f.tile, f.zchunk);
     f.state = state;
     f.partial = at<double>(work, L.partial);
@@ -198,6 +201,7 @@ hipError_t enqueue_fused_step(const FusedPlan &f, double dt, ns_diag *diag_out, 
 {
     StageArgs a = {};
     a.zchunk = f.zchunk;
+    a.order = f.order;
     a.qin = f.state;
     a.qout = f.b1;
     a.acc_out = f.acc;
@@ -273,6 +277,15 @@ ns_status ns_set_fused_config(int32_t tile, int32_t zchunk)
     return NS_OK;
 }
 
+ns_status ns_set_fused_order(int32_t order)
+{
+    if (order != 0 && order != 1) return NS_ERR_ARG;
+    g_order.store(order);
+    return NS_OK;
+}
+
+int32_t ns_get_fused_order(void) { return g_order.load(); }
+
 ns_status ns_get_fused_config(const ns_params *p, ns_precision prec, int32_t *tile,
                               int32_t *zchunk)
 {
@@ -310,7 +323,10 @@ ns_status ns_residual(const ns_params *p, ns_algo algo, const double *Q, double 
     if (algo == NS_ALGO_FUSED) {
         int tile, zc;
         choose_config(c, NS_FP64, &tile, &zc);
+        const int order = g_order.load();
+        if (!fused_order_supported(tile, order)) return NS_ERR_UNSUPPORTED;
         StageArgs a = {};
+        a.order = order;
         a.qin = Q;
         a.rout = R;
         a.mode = 0;

@@ -89,7 +89,11 @@ __device__ __forceinline__ float recip(float x)
     return __builtin_fmaf(r, e, r);
 }
 
-template <int BX, int BY, typename TIN, typename TOUT, typename CT, bool DIAG>
+// ORD selects the evaluation order of the in-plane residual terms (the
+// SN / SN2 distinction of the minimal-storage section): 0 groups them by
+// equation, the momentum equations by velocity component; 1 groups them by
+// derivative direction.  Same terms, different association of the sums.
+template <int BX, int BY, typename TIN, typename TOUT, typename CT, bool DIAG, int ORD>
 __global__ void __launch_bounds__(BX * BY)
 fused_stage_kernel(Consts c, StageArgs s)
 {
@@ -305,34 +309,75 @@ fused_stage_kernel(Consts c, StageArgs s)
                 // in-plane (x, y) part of the residual of this plane
                 const CT rhof = DEV ? CT(1) + rho : rho;
                 const CT uc = u * c1x, vc = v * c1y;
-                ra[S0][0] -= half * (c1x * DX1(L_M0) + c1y * DY1(L_M1) + rhof * a
-                                     + uc * DX1(L_RHO) + vc * DY1(L_RHO));
-                ra[S0][1] -= half * (c1x * DX1P(L_M0, L_U) + c1y * DY1P(L_M0, L_V) + m0 * a
-                                     + uc * DX1(L_M0) + vc * DY1(L_M0))
-                             + c1x * DX1(L_P);
-                ra[S0][2] -= half * (c1x * DX1P(L_M1, L_U) + c1y * DY1P(L_M1, L_V) + m1 * a
-                                     + uc * DX1(L_M1) + vc * DY1(L_M1))
-                             + c1y * DY1(L_P);
-                ra[S0][3] -= half * (c1x * DX1P(L_M2, L_U) + c1y * DY1P(L_M2, L_V) + m2 * a
-                                     + uc * DX1(L_M2) + vc * DY1(L_M2));
-                // viscous: d_j tau_ij = lap u_i + (1/3) d_i div u, in-plane parts
-                const CT Vx = four3 * (c2x * DX2(L_U)) + c2y * DY2(L_U)
-                              + third * (c1x * c1y * DXDY(L_V));
-                const CT Vy = c2x * DX2(L_V) + four3 * (c2y * DY2(L_V))
-                              + third * (c1x * c1y * DYDX(L_U));
-                const CT Vz = c2x * DX2(L_W) + c2y * DY2(L_W);
-                ra[S0][1] += inv_re * Vx;
-                ra[S0][2] += inv_re * Vy;
-                ra[S0][3] += inv_re * Vz;
                 // tau_ij du_i/dx_j restricted to terms without a z derivative
-                const CT phi = CT(2) * (Gxx * Gxx + Gyy * Gyy) + Gxy * Gxy + Gyx * Gyx
-                               + CT(2) * Gxy * Gyx + Gzx * Gzx + Gzy * Gzy;
-                // energy: skew convection, pressure work, viscous work,
-                // dissipation, heat conduction (x, y)
-                ra[S0][4] += -(c1x * DX1H() + c1y * DY1H())
-                             - half * (E * a + uc * DX1(L_E) + vc * DY1(L_E))
-                             + inv_re * (u * Vx + v * Vy + w * Vz + phi)
-                             + kappa * (c2x * DX2(L_T) + c2y * DY2(L_T));
+                auto in_plane_phi = [&]() {
+                    return CT(2) * (Gxx * Gxx + Gyy * Gyy) + Gxy * Gxy + Gyx * Gyx
+                           + CT(2) * Gxy * Gyx + Gzx * Gzx + Gzy * Gzy;
+                };
+                if constexpr (ORD == 0) {
+                    // grouped by equation (momentum by velocity component)
+                    ra[S0][0] -= half * (c1x * DX1(L_M0) + c1y * DY1(L_M1) + rhof * a
+                                         + uc * DX1(L_RHO) + vc * DY1(L_RHO));
+                    ra[S0][1] -= half * (c1x * DX1P(L_M0, L_U) + c1y * DY1P(L_M0, L_V) + m0 * a
+                                         + uc * DX1(L_M0) + vc * DY1(L_M0))
+                                 + c1x * DX1(L_P);
+                    ra[S0][2] -= half * (c1x * DX1P(L_M1, L_U) + c1y * DY1P(L_M1, L_V) + m1 * a
+                                         + uc * DX1(L_M1) + vc * DY1(L_M1))
+                                 + c1y * DY1(L_P);
+                    ra[S0][3] -= half * (c1x * DX1P(L_M2, L_U) + c1y * DY1P(L_M2, L_V) + m2 * a
+                                         + uc * DX1(L_M2) + vc * DY1(L_M2));
+                    // viscous: d_j tau_ij = lap u_i + (1/3) d_i div u, in-plane parts
+                    const CT Vx = four3 * (c2x * DX2(L_U)) + c2y * DY2(L_U)
+                                  + third * (c1x * c1y * DXDY(L_V));
+                    const CT Vy = c2x * DX2(L_V) + four3 * (c2y * DY2(L_V))
+                                  + third * (c1x * c1y * DYDX(L_U));
+                    const CT Vz = c2x * DX2(L_W) + c2y * DY2(L_W);
+                    ra[S0][1] += inv_re * Vx;
+                    ra[S0][2] += inv_re * Vy;
+                    ra[S0][3] += inv_re * Vz;
+                    const CT phi = in_plane_phi();
+                    // energy: skew convection, pressure work, viscous work,
+                    // dissipation, heat conduction (x, y)
+                    ra[S0][4] += -(c1x * DX1H() + c1y * DY1H())
+                                 - half * (E * a + uc * DX1(L_E) + vc * DY1(L_E))
+                                 + inv_re * (u * Vx + v * Vy + w * Vz + phi)
+                                 + kappa * (c2x * DX2(L_T) + c2y * DY2(L_T));
+                } else {
+                    // grouped by direction: every x derivative of every
+                    // equation, then every y derivative
+                    const CT phi = in_plane_phi();
+                    CT r0 = rhof * a, r1 = m0 * a, r2 = m1 * a, r3 = m2 * a, r4 = E * a;
+                    CT Vx = third * (c1x * c1y * DXDY(L_V));
+                    CT Vy = third * (c1x * c1y * DYDX(L_U));
+                    r0 += c1x * DX1(L_M0) + uc * DX1(L_RHO);
+                    r1 += c1x * DX1P(L_M0, L_U) + uc * DX1(L_M0);
+                    r2 += c1x * DX1P(L_M1, L_U) + uc * DX1(L_M1);
+                    r3 += c1x * DX1P(L_M2, L_U) + uc * DX1(L_M2);
+                    r4 += uc * DX1(L_E);
+                    CT h = c1x * DX1H();
+                    const CT px = c1x * DX1(L_P);
+                    Vx += four3 * (c2x * DX2(L_U));
+                    Vy += c2x * DX2(L_V);
+                    CT Vz = c2x * DX2(L_W);
+                    CT lapT = c2x * DX2(L_T);
+                    r0 += c1y * DY1(L_M1) + vc * DY1(L_RHO);
+                    r1 += c1y * DY1P(L_M0, L_V) + vc * DY1(L_M0);
+                    r2 += c1y * DY1P(L_M1, L_V) + vc * DY1(L_M1);
+                    r3 += c1y * DY1P(L_M2, L_V) + vc * DY1(L_M2);
+                    r4 += vc * DY1(L_E);
+                    h += c1y * DY1H();
+                    const CT py = c1y * DY1(L_P);
+                    Vx += c2y * DY2(L_U);
+                    Vy += four3 * (c2y * DY2(L_V));
+                    Vz += c2y * DY2(L_W);
+                    lapT += c2y * DY2(L_T);
+                    ra[S0][0] -= half * r0;
+                    ra[S0][1] += inv_re * Vx - (half * r1 + px);
+                    ra[S0][2] += inv_re * Vy - (half * r2 + py);
+                    ra[S0][3] += inv_re * Vz - half * r3;
+                    ra[S0][4] += -h - half * r4 + inv_re * (u * Vx + v * Vy + w * Vz + phi)
+                                 + kappa * lapT;
+                }
                 if constexpr (DIAG) ra[S0][NR - 1] = Gyx - Gxy;   // omega_z
             }
         }
@@ -483,8 +528,8 @@ fused_stage_kernel(Consts c, StageArgs s)
 // ---------------------------------------------------------------------------
 // Host-side launch helpers
 
-template <int BX, int BY, typename TIN, typename TOUT, typename CT>
-static hipError_t launch_t(const Consts &c, const StageArgs &s, hipStream_t st)
+template <int BX, int BY, typename TIN, typename TOUT, typename CT, int ORD>
+static hipError_t launch_o(const Consts &c, const StageArgs &s, hipStream_t st)
 {
     dim3 block(BX, BY, 1);
     dim3 grid((c.nx + BX - 1) / BX, (c.ny + BY - 1) / BY, (c.nz + s.zchunk - 1) / s.zchunk);
@@ -492,13 +537,25 @@ static hipError_t launch_t(const Consts &c, const StageArgs &s, hipStream_t st)
     // double state
     if constexpr (std::is_same<TIN, double>::value) {
         if (s.diag_partial != nullptr && s.mode == 1) {
-            hipLaunchKernelGGL((fused_stage_kernel<BX, BY, TIN, TOUT, CT, true>), grid, block, 0, st,
-                               c, s);
+            hipLaunchKernelGGL((fused_stage_kernel<BX, BY, TIN, TOUT, CT, true, ORD>), grid, block, 0,
+                               st, c, s);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((fused_stage_kernel<BX, BY, TIN, TOUT, CT, false>), grid, block, 0, st, c, s);
+    hipLaunchKernelGGL((fused_stage_kernel<BX, BY, TIN, TOUT, CT, false, ORD>), grid, block, 0, st, c,
+                       s);
     return hipGetLastError();
+}
+
+// The direction-grouped order is compiled for the default tile of each
+// precision only (16x8 and 32x8); order_supported() tells the host.
+template <int BX, int BY, typename TIN, typename TOUT, typename CT>
+static hipError_t launch_t(const Consts &c, const StageArgs &s, hipStream_t st)
+{
+    if (s.order == 0) return launch_o<BX, BY, TIN, TOUT, CT, 0>(c, s, st);
+    if constexpr ((BX == 16 && BY == 8) || (BX == 32 && BY == 8))
+        return launch_o<BX, BY, TIN, TOUT, CT, 1>(c, s, st);
+    return hipErrorInvalidValue;
 }
 
 template <typename TIN, typename TOUT, typename CT>
@@ -529,6 +586,11 @@ void tile_dims(int tile, int *bx, int *by)
     case TILE_8x8: *bx = 8; *by = 8; break;
     default: *bx = 32; *by = 8; break;
     }
+}
+
+bool fused_order_supported(int tile, int order)
+{
+    return order == 0 || (order == 1 && (tile == TILE_16x8 || tile == TILE_32x8));
 }
 
 int64_t fused_num_blocks(const Consts &c, int tile, int zchunk)

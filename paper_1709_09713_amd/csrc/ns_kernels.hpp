@@ -23,10 +23,12 @@ struct StageArgs {
     int mode;               // 0 = residual, 1..3 = RK stage
     int zchunk;             // planes per block along z
     double *diag_partial;   // per-block diagnostic partial sums, or nullptr
+    int order;              // in-plane evaluation order: 0 by equation, 1 by direction
 };
 
 void tile_dims(int tile, int *bx, int *by);
 int64_t fused_num_blocks(const Consts &c, int tile, int zchunk);
+bool fused_order_supported(int tile, int order);
 hipError_t launch_fused_stage(const Consts &c, const StageArgs &s, ns_precision prec,
                               int tile, hipStream_t st);
 
@@ -36,7 +38,7 @@ hipError_t launch_fused_stage(const Consts &c, const StageArgs &s, ns_precision 
 struct FusedPlan {
     Consts c;
     ns_precision prec;
-    int tile, zchunk;
+    int tile, zchunk, order;
     int64_t nblk;
     double *state, *partial, *acc;
     void *b1, *b2;

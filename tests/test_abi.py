@@ -185,3 +185,22 @@ def test_instance_struct_matches_header():
     assert tuple(names) == tuple(f for f, _ in nat.ns_instance._fields_)
     assert nat.ns_instance.tile.offset == nat.ns_instance.steps.offset + 4
     assert nat.ns_instance.state.offset % 8 == 0
+
+
+def test_fused_order_validation():
+    assert ns.ns_get_fused_order() == 0
+    with pytest.raises(ns.NativeError) as e:
+        ns.ns_set_fused_order(2)
+    assert e.value.status == ns.NS_ERR_ARG
+    p = ns.make_params(16)
+    wb = ns.ns_workspace_bytes(p, ns.NS_ALGO_FUSED, ns.NS_FP64)
+    try:
+        ns.ns_set_fused_order(1)
+        assert ns.ns_get_fused_order() == 1
+        ns.ns_set_fused_config(1, 0)            # 16x16: order 1 is not compiled for it
+        with pytest.raises(ns.NativeError) as e:
+            ns.rk3_step(p, ns.NS_ALGO_FUSED, ns.NS_FP64, 1e-3, 1, 0x1000, 0x100000, wb)
+        assert e.value.status == ns.NS_ERR_UNSUPPORTED
+    finally:
+        ns.ns_set_fused_config(-1, 0)
+        ns.ns_set_fused_order(0)

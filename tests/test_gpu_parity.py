@@ -194,6 +194,34 @@ def test_fp32_tilings_match_oracle_and_zchunk_is_bitwise(ns):
         ns.ns_set_fused_config(-1, 0)
 
 
+def test_evaluation_orders_match_oracle(ns):
+    """Both in-plane evaluation orders (by equation / by direction) match the
+    oracle, in FP64 (16x8) and FP32 storage (32x8), and agree with each
+    other to rounding."""
+    n = (37, 21, 19)
+    Q0 = synth.random_state(n[::-1], seed=11)
+    ph = phys(n, mach=0.2)
+    p = params(ns, n, mach=0.2)
+    want = oracle.rk3(ph, Q0, 1e-3, 2)
+    wantR = oracle.residual(ph, Q0)
+    try:
+        for prec, tile, tol in ((ns.NS_FP64, 4, TOL), (ns.NS_FP32_STORE, 0, 1e-5)):
+            got = {}
+            for order in (0, 1):
+                print(f"order {order} prec {prec} tile {tile}", flush=True)
+                ns.ns_set_fused_config(tile, 0)
+                ns.ns_set_fused_order(order)
+                got[order] = gpu_rk3(ns, p, ns.NS_ALGO_FUSED, prec, Q0, 1e-3, 2)
+                assert max(rel(got[order], want)) < tol, (prec, order)
+                if prec == ns.NS_FP64:
+                    R = gpu_residual(ns, p, ns.NS_ALGO_FUSED, Q0)
+                    assert max(rel(R, wantR)) < tol_residual(n), order
+            assert max(rel(got[1], got[0])) < tol
+    finally:
+        ns.ns_set_fused_config(-1, 0)
+        ns.ns_set_fused_order(0)
+
+
 def test_diagnostics_standalone(ns):
     n = (24, 20, 18)
     Q = synth.random_state(n[::-1], seed=5)
