@@ -61,15 +61,52 @@ def summarize(results, t_first, t_last):
             "requests_per_s": len(results) / span}
 
 
+class GpuBackend:
+    """What the server needs from the device: a batch, stream events, a
+    side stream, final diagnostics and member footprints."""
+
+    def __init__(self, precision: str, max_instances: int, nstreams: int):
+        self.precision = precision
+        self.max_instances = max_instances
+        self.nstreams = nstreams
+
+    def stream(self):
+        return torch.cuda.current_stream()
+
+    def side_stream(self):
+        return torch.cuda.Stream()
+
+    def batch(self):
+        return Batch(self.max_instances, self.precision, nstreams=self.nstreams)
+
+    def event(self, stream):
+        ev = torch.cuda.Event()
+        ev.record(stream)
+        return ev
+
+    def diagnostics(self, p, state, work, side, ev):
+        side.wait_event(ev)
+        return nat.diagnostics(p, state, work, stream=side)
+
+    def footprint(self, n) -> int:
+        return Batch.footprint(n, self.precision)
+
+    def free_bytes(self) -> int:
+        return torch.cuda.mem_get_info()[0]
+
+    def host_state(self, state):
+        return state.cpu().numpy()
+
+
 class Server:
     def __init__(self, precision: str = "fp32", max_instances: int = 64,
                  hbm_budget: int | None = None, nstreams: int = 4, quantum: int = 25,
-                 tuner=None, keep_states: bool = False):
+                 tuner=None, keep_states: bool = False, backend=None):
         self.precision = precision
         self.max_instances = max_instances
+        self.backend = backend or GpuBackend(precision, max_instances, nstreams)
         if hbm_budget is None:
-            free, _ = torch.cuda.mem_get_info()
-            hbm_budget = min(32 << 30, free // 2)
+            hbm_budget = min(32 << 30, self.backend.free_bytes() // 2)
         self.hbm_budget = hbm_budget
         self.nstreams = nstreams
         self.quantum = quantum
@@ -80,12 +117,13 @@ class Server:
         """Serve `requests` (dicts with rid, arrival [s from start], n,
         reynolds, mach, dt, steps) in real time; returns (results sorted by
         rid, summary)."""
-        stream = torch.cuda.current_stream()
-        side = torch.cuda.Stream()
-        batch = Batch(self.max_instances, self.precision, nstreams=self.nstreams)
+        be = self.backend
+        stream = be.stream()
+        side = be.side_stream()
+        batch = be.batch()
         pending = collections.deque(sorted(requests, key=lambda r: r["arrival"]))
         for r in pending:
-            if Batch.footprint(r["n"], self.precision) > self.hbm_budget:
+            if be.footprint(r["n"]) > self.hbm_budget:
                 raise ValueError(f"request {r['rid']} alone exceeds the HBM budget")
         active = {}     # slot -> [req, admitted, steps_left]
         draining = []   # (event, req, admitted, params, state, work)
@@ -104,13 +142,12 @@ class Server:
             for item in draining:
                 ev, req, adm, p, state, work = item
                 if force or ev.query():
-                    side.wait_event(ev)
-                    d = nat.diagnostics(p, state, work, stream=side)
+                    d = be.diagnostics(p, state, work, side, ev)
                     res = Result(req["rid"], req["n"], req["steps"], req["arrival"], adm, now(), d)
                     if self.keep_states:
-                        res.state = state.cpu().numpy()
+                        res.state = be.host_state(state)
                     results.append(res)
-                    used -= Batch.footprint(req["n"], self.precision)
+                    used -= be.footprint(req["n"])
                 else:
                     keep.append(item)
             draining[:] = keep
@@ -122,7 +159,7 @@ class Server:
                 while (pending and pending[0]["arrival"] <= now()
                        and len(active) < self.max_instances):
                     req = pending[0]
-                    fp = Batch.footprint(req["n"], self.precision)
+                    fp = be.footprint(req["n"])
                     if used + fp > self.hbm_budget:
                         break
                     pending.popleft()
@@ -141,8 +178,7 @@ class Server:
                     continue
                 q = min(self.quantum, min(a[2] for a in active.values()))
                 batch.step(q, stream)
-                ev = torch.cuda.Event()
-                ev.record(stream)
+                ev = be.event(stream)
                 for slot in list(active):
                     a = active[slot]
                     a[2] -= q

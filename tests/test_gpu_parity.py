@@ -360,3 +360,25 @@ def test_256_fused_vs_stored_states_and_conservation(ns):
         e = rel(out["fused"], out[other])
         print(f"256^3x20 fused vs {other}: rel={max(e):.2e}", flush=True)
         assert max(e) < TOL, (other, e)
+
+
+@pytest.mark.parametrize("algo", ["fused", "stored", "some"])
+def test_discrete_conservation_on_gpu(ns, algo):
+    """On the periodic grid the GPU residual conserves mass and momentum for
+    any state, and energy when inviscid, to rounding: |sum R_f| stays at the
+    rounding level of N * max|R_f| (a dropped or mis-signed flux term would
+    leave a sum of order N * max|R_f|)."""
+    n = (48, 40, 36)
+    Q = synth.random_state(n[::-1], seed=21)
+    npts = n[0] * n[1] * n[2]
+    for re in (1600.0, math.inf):
+        p = params(ns, n, reynolds=re, mach=0.2)
+        R = gpu_residual(ns, p, ns.ALGOS[algo], Q)
+        for f in range(5):
+            if f == 4 and math.isfinite(re):
+                continue    # the viscous energy terms leak O(h^4) (pinned on the oracle)
+            s = abs(R[f].sum())
+            bound = 64 * np.finfo(np.float64).eps * npts * np.abs(R[f]).max()
+            assert s < bound, (algo, re, f, s, bound)
+            # and the bound is far below a real leak
+            assert bound < 1e-6 * npts * np.abs(R[f]).max()
