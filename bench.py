@@ -101,9 +101,23 @@ class Run:
         torch.cuda.empty_cache()
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(n, steps=1):
     """The FP64 oracle as it stands, on this host's cores: `steps` RK3 steps
-    of the n^3 TGV (a bounded sample of the benchmark workload)."""
+    of the n^3 TGV (a bounded sample of the benchmark workload), plus its
+    single-thread rate on the 16^3 TGV (10 steps, in a child process with
+    one OpenMP thread)."""
+    import subprocess
     import oracle
     ph = oracle.Physics(n=(n, n, n))
     Q = oracle.tgv_init(ph)
@@ -111,9 +125,21 @@ def cpu_baseline(n, steps=1):
     t0 = time.perf_counter()
     oracle.rk3(ph, Q, synth.stable_dt(n, 0.1), steps)
     sec = time.perf_counter() - t0
+    one = None
+    code = ("import time, oracle; ph = oracle.Physics(n=(16, 16, 16)); Q = oracle.tgv_init(ph); "
+            "t = time.perf_counter(); oracle.rk3(ph, Q, 3.385e-3, 10); "
+            "print(16 ** 3 * 3 * 10 / (time.perf_counter() - t))")
+    try:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                             text=True, timeout=120, check=True)
+        one = float(out.stdout.strip().splitlines()[-1])
+    except (subprocess.SubprocessError, ValueError, IndexError):
+        one = None
     return {"value": n ** 3 * 3 * steps / sec, "unit": "updates/s", "cores": threads,
             "kind": "oracle", "sample": f"{steps} RK3 step(s) of the {n}^3 TGV (FP64, C oracle, "
-            f"OpenMP over z-planes), {sec:.1f} s"}
+            f"OpenMP over z-planes), {sec:.1f} s",
+            "cpu_model": cpu_model(), "single_thread_updates_per_s_16cubed": one}
 
 
 def batched(tuner, seed=0, count=64, steps=200):
@@ -219,11 +245,16 @@ def serving(tuner, seed=0, count=48, rate=50.0):
         f"p99 {s64['p99_latency_s']:.2f} s {s64['updates_per_s']:.3e} updates/s")
     torch.cuda.empty_cache()
     offered = sum(r["n"] ** 3 * 3 * r["steps"] for r in reqs) / (reqs[-1]["arrival"] or 1.0)
+    # capacity: what the batched server completes per second when saturated
+    # (this stream keeps it saturated from the first second on)
+    capacity = s32["updates_per_s"]
     return {"requests": count, "seed": seed, "rate_hz": rate,
             "offered_updates_per_s": offered, "hbm_budget_bytes": srv.hbm_budget,
             "max_instances": srv.max_instances, "quantum_steps": srv.quantum,
             "continuous_batching_fp32": s32, "sequential_fp64": s64,
             "throughput_ratio": s32["updates_per_s"] / s64["updates_per_s"],
+            "offered_over_capacity": offered / capacity,
+            "sustainable_rate_hz": rate * capacity / offered,
             "error_bound_fp32_vs_fp64_oracle": 1e-5}
 
 
