@@ -142,6 +142,47 @@ def cpu_baseline(n, steps=1):
             "cpu_model": cpu_model(), "single_thread_updates_per_s_16cubed": one}
 
 
+def fp32_error_512(n=512, steps=50):
+    """The 512^3 TGV (Re 1600, M 0.1) advanced `steps` steps with the fused
+    kernel in FP64 and in FP32 storage; per-field relative error of FP32
+    storage against FP64 (max|x - x64| / max|x64|, the momentum components
+    sharing the momentum vector's scale).  The FP64 path stands for the
+    oracle here: it matches the oracle to 1e-12 wherever the oracle can run
+    (and on sampled 512^3 residuals); the oracle itself would need tens of
+    minutes for these 50 steps."""
+    p = ns.make_params(n)
+    dt = synth.stable_dt(n, 0.1)
+    out = {}
+    states = {}
+    for prec in ("fp64", "fp32"):
+        st = torch.empty((5, n, n, n), dtype=torch.float64, device="cuda")
+        wk = torch.empty(ns.ns_workspace_bytes(p, ns.NS_ALGO_FUSED, ns.PRECS[prec]),
+                         dtype=torch.uint8, device="cuda")
+        ns.tgv_init(p, st)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ns.rk3_step(p, ns.NS_ALGO_FUSED, ns.PRECS[prec], dt, steps, st, wk)
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"{prec}_updates_per_s"] = n ** 3 * 3 * steps / (e0.elapsed_time(e1) * 1e-3)
+        states[prec] = st
+        del wk
+        torch.cuda.empty_cache()
+    a, b = states["fp32"], states["fp64"]
+    scale = [b[v].abs().max().item() for v in range(5)]
+    mom = max(scale[1:4])
+    scale[1:4] = [mom] * 3
+    err = [((a[v] - b[v]).abs().max().item() / scale[v]) for v in range(5)]
+    del states, a, b
+    torch.cuda.empty_cache()
+    out.update({"n": n, "steps": steps, "dt": dt, "fp32_rel_error_per_field": err,
+                "fp32_rel_error_max": max(err),
+                "reference": "fused FP64 GPU path (oracle parity 1e-12 at all oracle-feasible sizes)"})
+    log(f"bench 512^3 x{steps}: FP32 storage rel error vs FP64 {max(err):.2e}")
+    return out
+
+
 def batched(tuner, seed=0, count=64, steps=200):
     """64 independent TGV instances (N from {32,48,64,96,128}, Re ~ U[400,
     3200], M ~ U[0.05, 0.4]), `steps` RK3 steps each: one batch in FP32
@@ -348,6 +389,11 @@ def main():
         variants["fused_over_stored_256"] = value / variants[f"stored_fp64_{n}"]["updates_per_s"]
         variants["fused_over_some_512"] = f512 / variants["some_fp64_512"]["updates_per_s"]
 
+    c512 = None
+    if not args.no_variants:
+        log("bench: 512^3 x 50 FP32-storage error")
+        c512 = fp32_error_512()
+
     batch_out = serve_out = None
     if not (args.no_batched and args.no_serving):
         from paper_1709_09713_amd.autotune import Autotuner
@@ -395,6 +441,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,
+        "tgv512_fp32_error": c512,
         "batched": batch_out,
         "serving": serve_out,
         "energy": energy_out,

@@ -382,3 +382,22 @@ def test_discrete_conservation_on_gpu(ns, algo):
             assert s < bound, (algo, re, f, s, bound)
             # and the bound is far below a real leak
             assert bound < 1e-6 * npts * np.abs(R[f]).max()
+
+
+def test_fp32_storage_long_run_error_vs_fp64(ns):
+    """128^3 TGV, 50 steps: FP32 storage stays within 1e-5 of the FP64 path
+    (which is pinned to the oracle), and the two differ (not a silent FP64
+    run)."""
+    n = (128, 128, 128)
+    p = params(ns, n)
+    dt = synth.stable_dt(128, 0.1)
+    got = {}
+    for prec in (ns.NS_FP64, ns.NS_FP32_STORE):
+        Qd = torch.empty((5, 128, 128, 128), dtype=torch.float64, device="cuda")
+        ns.tgv_init(p, Qd)
+        ns.rk3_step(p, ns.NS_ALGO_FUSED, prec, dt, 50, Qd, work_for(ns, p, ns.NS_ALGO_FUSED, prec))
+        torch.cuda.synchronize()
+        got[prec] = Qd.cpu().numpy()
+    e = rel(got[ns.NS_FP32_STORE], got[ns.NS_FP64])
+    print(f"128^3x50 fp32-store vs fp64: rel per field {['%.2e' % x for x in e]}", flush=True)
+    assert 1e-12 < max(e) < 1e-5, e
