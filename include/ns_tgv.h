@@ -155,8 +155,10 @@ ns_status diagnostics(const ns_params *p, const double *state,
  * (x, y) column tile of one block: 0 = 32x8, 1 = 16x16, 2 = 64x4,
  * 3 = 32x16, 4 = 16x8, 5 = 32x4, 6 = 16x4, 7 = 8x8 (threads = product, one
  * z column each); zchunk is the number of
- * z planes one block marches through (>= 4; 0 = automatic).  tile = -1
- * restores the automatic choice.  For a given tile, residuals and states
+ * z planes one block marches through (>= 4; 0 = automatic: the length that
+ * minimises (rounds of device-resident blocks) x (planes each block
+ * marches, chunk + 4 halo planes)).  tile = -1 restores the automatic
+ * choice.  For a given tile, residuals and states
  * are bitwise independent of zchunk; different tiles are separate compiled
  * instances and may differ at the rounding level (the compiler can contract
  * a multiply-add differently); per-step diagnostics also differ in the

@@ -97,4 +97,5 @@ class Autotuner:
         dflt = [t for t, tl, z in timings if z == 0 and tl == dtile]
         return {"tile": tile, "zchunk": zc, "ms_per_step": best,
                 "default_ms_per_step": dflt[0] if dflt else None,
-                "candidates": len(timings), "tune_seconds": time.perf_counter() - t_wall}
+                "candidates": len(timings), "tune_seconds": time.perf_counter() - t_wall,
+                "ranking": [[round(t, 5), tl, z] for t, tl, z in timings[:6]]}

@@ -43,10 +43,38 @@ static std::atomic<int> g_tile{-1};
 static std::atomic<int> g_zchunk{0};
 static std::atomic<int> g_order{0};
 
+// Default z-chunk: a block marches zchunk + 4 planes (padded to the unroll
+// of 5), and the grid runs in ceil(blocks / resident) rounds of resident
+// blocks, so the time of a stage goes as rounds x padded planes.  Pick the
+// number of chunks along z that minimises it (fewest blocks on a tie).
+// resident = blocks the device holds at once (512 on MI355X for the default
+// tiles); when it cannot be queried, 512 is assumed.
+static int default_zchunk(const Consts &c, ns_precision prec, int tile)
+{
+    int bx, by;
+    tile_dims(tile, &bx, &by);
+    const int64_t nxy = (int64_t)((c.nx + bx - 1) / bx) * ((c.ny + by - 1) / by);
+    int64_t resident = fused_resident_blocks(prec, tile);
+    if (resident <= 0) resident = 512;
+    int best_z = c.nz;
+    int64_t best_cost = -1;
+    for (int k = 1; k <= c.nz / kMinZChunk; ++k) {
+        const int z = (c.nz + k - 1) / k;
+        const int chunks = (c.nz + z - 1) / z;
+        if (chunks != k) continue;   // the same z as a smaller k
+        const int64_t rounds = (chunks * nxy + resident - 1) / resident;
+        const int64_t planes = ((z + 4 + 4) / 5) * 5;
+        const int64_t cost = rounds * planes;
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best_z = z;
+        }
+    }
+    return best_z;
+}
+
 // Launch shape: an explicit tile (>= 0) / zchunk (> 0) wins, else the
-// process-wide setting of ns_set_fused_config, else the default.  The z
-// march is unrolled by 5 over zchunk + 4 planes, so chunks of 5k + 1 planes
-// carry no padding planes.
+// process-wide setting of ns_set_fused_config, else the default.
 static void choose_config(const Consts &c, ns_precision prec, int tile_in, int zchunk_in, int *tile,
                           int *zchunk)
 {
@@ -54,16 +82,7 @@ static void choose_config(const Consts &c, ns_precision prec, int tile_in, int z
     int z = tile_in >= 0 ? zchunk_in : g_zchunk.load();
     if (zchunk_in > 0) z = zchunk_in;
     if (t < 0 || t >= TILE_COUNT) t = (prec == NS_FP64) ? TILE_16x8 : TILE_32x8;
-    if (z <= 0) {
-        int bx, by;
-        tile_dims(t, &bx, &by);
-        const int64_t xy = (int64_t)((c.nx + bx - 1) / bx) * ((c.ny + by - 1) / by);
-        const int64_t want = 2048;
-        const int64_t nzc = (want + xy - 1) / xy;
-        z = (int)((c.nz + nzc - 1) / nzc);
-        if (z < 16) z = 16;
-        z = ((z + 3) / 5) * 5 + 1;
-    }
+    if (z <= 0) z = default_zchunk(c, prec, t);
     if (z < kMinZChunk) z = kMinZChunk;
     if (z > c.nz) z = c.nz;
     *tile = t;

@@ -40,6 +40,7 @@
 // parts are applied analytically (stencil coefficients sum to zero: only
 // H_ref div u survives, added in double), and the RK accumulator stays
 // double.
+#include <atomic>
 #include <type_traits>
 
 #include "ns_common.hpp"
@@ -586,6 +587,55 @@ void tile_dims(int tile, int *bx, int *by)
     case TILE_8x8: *bx = 8; *by = 8; break;
     default: *bx = 32; *by = 8; break;
     }
+}
+
+// Blocks of one stage kernel instance that the device holds at once
+// (compute units x occupancy per compute unit); 0 if it cannot be queried.
+template <int BX, int BY, typename TIN, typename TOUT, typename CT>
+static int resident_t()
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, reinterpret_cast<const void *>(&fused_stage_kernel<BX, BY, TIN, TOUT, CT, false, 0>),
+            BX * BY, 0) != hipSuccess)
+        return 0;
+    return cus * (per > 0 ? per : 1);
+}
+
+template <typename TIN, typename TOUT, typename CT>
+static int resident_tile(int tile)
+{
+    switch (tile) {
+    case TILE_32x8: return resident_t<32, 8, TIN, TOUT, CT>();
+    case TILE_16x16: return resident_t<16, 16, TIN, TOUT, CT>();
+    case TILE_64x4: return resident_t<64, 4, TIN, TOUT, CT>();
+    case TILE_32x16: return resident_t<32, 16, TIN, TOUT, CT>();
+    case TILE_16x8: return resident_t<16, 8, TIN, TOUT, CT>();
+    case TILE_32x4: return resident_t<32, 4, TIN, TOUT, CT>();
+    case TILE_16x4: return resident_t<16, 4, TIN, TOUT, CT>();
+    case TILE_8x8: return resident_t<8, 8, TIN, TOUT, CT>();
+    default: return 0;
+    }
+}
+
+int fused_resident_blocks(ns_precision prec, int tile)
+{
+    if (tile < 0 || tile >= TILE_COUNT) return 0;
+    // queried once per (device, precision, tile)
+    constexpr int kMaxDev = 16;
+    static std::atomic<int> cache[kMaxDev][2][TILE_COUNT];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return 0;
+    const int q = prec == NS_FP64 ? 0 : 1;
+    int r = cache[dev][q][tile].load();
+    if (r == 0) {
+        r = prec == NS_FP64 ? resident_tile<double, double, double>(tile)
+                            : resident_tile<float, float, float>(tile);
+        if (r > 0) cache[dev][q][tile].store(r);
+    }
+    return r;
 }
 
 bool fused_order_supported(int tile, int order)

@@ -29,6 +29,9 @@ struct StageArgs {
 void tile_dims(int tile, int *bx, int *by);
 int64_t fused_num_blocks(const Consts &c, int tile, int zchunk);
 bool fused_order_supported(int tile, int order);
+// Stage-kernel blocks resident on the current device at once (0 if the
+// device cannot be queried).
+int fused_resident_blocks(ns_precision prec, int tile);
 hipError_t launch_fused_stage(const Consts &c, const StageArgs &s, ns_precision prec,
                               int tile, hipStream_t st);
 
