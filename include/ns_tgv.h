@@ -191,9 +191,11 @@ int32_t ns_get_fused_order(void);
  * Each member runs exactly the launches of rk3_step with the fused class
  * (residual of the governing-equations section, RK3 of the time-advancement
  * section) under its own launch shape; a batch step queues one RK3 step of
- * every member with steps left, members spread over up to 4 internal HIP
- * streams (balanced by grid points) that fork from and join back into the
- * caller's stream, so small grids overlap on the device.  Per-point
+ * every member with steps left (largest grids first), members spread over
+ * up to 4 internal HIP streams (balanced by grid points) that fork from and
+ * join back into the caller's stream, so small grids overlap on the device.
+ * With the caller's stream that is up to 5 streams: on a device with 4
+ * hardware queues per process, 3 internal streams measured fastest.  Per-point
  * arithmetic never depends on the other members: a solve gives identical
  * bits alone and in any mix.  Solves join (ns_batch_add) and leave
  * (ns_batch_remove) between steps while the others keep their state.

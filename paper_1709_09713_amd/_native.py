@@ -234,7 +234,7 @@ def ns_get_fused_order() -> int:
 # ---------------------------------------------------------------------------
 # Batched execution (ns_batch_*)
 
-def ns_batch_create(max_instances: int, prec: int, nstreams: int = 4,
+def ns_batch_create(max_instances: int, prec: int, nstreams: int = 3,
                     with_diagnostics: bool = False) -> int:
     h = ctypes.c_void_p()
     _check(lib().ns_batch_create(int(max_instances), int(prec), int(nstreams),

@@ -12,7 +12,7 @@ from . import _native as nat
 
 
 class Batch:
-    def __init__(self, max_instances: int, precision: str = "fp32", nstreams: int = 4,
+    def __init__(self, max_instances: int, precision: str = "fp32", nstreams: int = 3,
                  diagnostics: bool = False, device="cuda"):
         self.prec = nat.PRECS[precision]
         self.precision = precision

@@ -8,6 +8,7 @@
 // from and join back into the caller's stream, so the batch is ordered like
 // any other stream work.  The launches are exactly rk3_step's, so a
 // member's result does not depend on which other members share the batch.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -177,12 +178,20 @@ ns_status ns_batch_step(ns_batch *b, int32_t nsteps, void *stream)
     if (!any || nsteps == 0) return NS_OK;
     NS_HIP_OK(hipEventRecord(b->fork, caller));
     for (int s = 0; s < b->nstreams; ++s) NS_HIP_OK(hipStreamWaitEvent(b->streams[s], b->fork, 0));
+    // Largest members first within a step, so that small grids (which
+    // cannot fill the device alone) run beside large ones on the other
+    // streams.
+    std::vector<int> order;
+    for (int i = 0; i < b->max_inst; ++i)
+        if (b->m[i].used) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return b->m[x].points > b->m[y].points; });
     // Step-major order: every member's step k is queued before any step
     // k + 1, so each internal stream is fed as the host walks the list.
     for (int32_t k = 0; k < nsteps; ++k) {
-        for (int i = 0; i < b->max_inst; ++i) {
+        for (int i : order) {
             Member &m = b->m[i];
-            if (!m.used || m.steps_left <= 0) continue;
+            if (m.steps_left <= 0) continue;
             ns_diag *d = b->diag ? b->d_diag + i : nullptr;
             NS_HIP_OK(enqueue_fused_step(m.plan, m.dt, d, b->streams[m.stream]));
             --m.steps_left;

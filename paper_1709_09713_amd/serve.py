@@ -100,7 +100,7 @@ class GpuBackend:
 
 class Server:
     def __init__(self, precision: str = "fp32", max_instances: int = 64,
-                 hbm_budget: int | None = None, nstreams: int = 4, quantum: int = 25,
+                 hbm_budget: int | None = None, nstreams: int = 3, quantum: int = 25,
                  tuner=None, keep_states: bool = False, backend=None):
         self.precision = precision
         self.max_instances = max_instances
