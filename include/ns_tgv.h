@@ -192,7 +192,7 @@ int32_t ns_get_fused_order(void);
  * (residual of the governing-equations section, RK3 of the time-advancement
  * section) under its own launch shape; a batch step queues one RK3 step of
  * every member with steps left (largest grids first), members spread over
- * up to 4 internal HIP streams (balanced by grid points) that fork from and
+ * up to 8 internal HIP streams (balanced by grid points) that fork from and
  * join back into the caller's stream, so small grids overlap on the device.
  * With the caller's stream that is up to 5 streams: on a device with 4
  * hardware queues per process, 3 internal streams measured fastest.  Per-point
@@ -219,7 +219,7 @@ typedef struct {
 } ns_instance;
 
 /* Create a batch with room for max_instances (1..4096) solves advanced in
- * precision prec over nstreams (1..4) internal streams; with_diagnostics
+ * precision prec over nstreams (1..8) internal streams; with_diagnostics
  * != 0 computes each member's diagnostics of the state at the start of
  * every step it runs (last one readable with ns_batch_poll).  Allocates
  * streams, events and the diagnostics array (NS_ERR_DEVICE on failure);

@@ -19,7 +19,7 @@
 
 namespace ns {
 
-constexpr int kMaxStreams = 4;
+constexpr int kMaxStreams = 8;
 constexpr int kMaxInstances = 4096;
 
 struct Member {

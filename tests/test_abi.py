@@ -161,7 +161,7 @@ def test_package_has_no_cpu_fallback():
 
 def test_batch_create_validates_before_touching_the_device():
     # (max_instances, precision, nstreams, with_diagnostics)
-    for args in ((0, 0, 1, 0), (4097, 0, 1, 0), (4, 5, 1, 0), (4, 0, 0, 0), (4, 0, 5, 0)):
+    for args in ((0, 0, 1, 0), (4097, 0, 1, 0), (4, 5, 1, 0), (4, 0, 0, 0), (4, 0, 9, 0)):
         with pytest.raises(ns.NativeError) as e:
             ns.ns_batch_create(*args)
         assert e.value.status == ns.NS_ERR_ARG
