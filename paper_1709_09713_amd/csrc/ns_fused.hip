@@ -59,13 +59,17 @@ __device__ __forceinline__ CT to_ct(TIN v, double ref)
         return v;
 }
 
+// Stage outputs and the accumulator are streamed: written (or read) once
+// per stage and not touched again before the next stage, which rereads them
+// from HBM anyway.  Non-temporal accesses keep them from displacing the
+// input planes in L2, whose halo rows neighbouring blocks read again.
 template <typename TOUT>
 __device__ __forceinline__ void store_q(void *q, int64_t i, double v, double ref)
 {
     if constexpr (std::is_same<TOUT, double>::value)
-        ((double *)q)[i] = v;
+        __builtin_nontemporal_store(v, (double *)q + i);
     else
-        ((float *)q)[i] = (float)(v - ref);
+        __builtin_nontemporal_store((float)(v - ref), (float *)q + i);
 }
 
 template <int V>
@@ -231,7 +235,7 @@ fused_stage_kernel(Consts c, StageArgs s)
             const int zc = fin ? zf : z0;
             const int64_t pidx = (int64_t)zc * c.nxy + (active ? col : 0);
 #pragma unroll
-            for (int f = 0; f < 5; ++f) accpf[f] = src[f * N + pidx];
+            for (int f = 0; f < 5; ++f) accpf[f] = __builtin_nontemporal_load(src + f * N + pidx);
         }
         load_plane(zp + 1);
 
@@ -474,7 +478,8 @@ fused_stage_kernel(Consts c, StageArgs s)
 #pragma unroll
                 for (int f = 0; f < 5; ++f) {
                     store_q<TOUT>(s.qout, f * N + pidx, accpf[f] + s.a_dt * Rd[f], ref[f]);
-                    if (s.mode < 3) s.acc_out[f * N + pidx] = accpf[f] + s.b_dt * Rd[f];
+                    if (s.mode < 3)
+                        __builtin_nontemporal_store(accpf[f] + s.b_dt * Rd[f], s.acc_out + f * N + pidx);
                 }
             }
         }
