@@ -65,14 +65,16 @@ def log(msg):
 
 class Run:
     def __init__(self, n, algo, prec, reynolds=1600.0, mach=0.1):
+        shape = (n, n, n) if isinstance(n, int) else tuple(n)
         self.n = n
-        self.p = ns.make_params(n, reynolds=reynolds, mach=mach)
+        self.points = shape[0] * shape[1] * shape[2]
+        self.p = ns.make_params(shape, reynolds=reynolds, mach=mach)
         self.algo = ns.ALGOS[algo]
         self.prec = ns.PRECS[prec]
-        self.state = torch.empty((5, n, n, n), dtype=torch.float64, device="cuda")
+        self.state = torch.empty((5, shape[2], shape[1], shape[0]), dtype=torch.float64, device="cuda")
         wb = ns.ns_workspace_bytes(self.p, self.algo, self.prec)
         self.work = torch.empty(wb, dtype=torch.uint8, device="cuda")
-        self.dt = synth.stable_dt(n, mach)
+        self.dt = synth.stable_dt(max(shape), mach)
         self.stream = torch.cuda.current_stream()
         ns.tgv_init(self.p, self.state, self.stream)
 
@@ -383,6 +385,13 @@ def main():
             variants[f"fused_{vp}_{n}_order_by_direction"] = {
                 "updates_per_s": n ** 3 * 3 * K / (vms * 1e-3), "ms_per_step": vms / K, "steps": K,
                 "tile": tile}
+        # one GPU's share of a 512^3 grid in 8 z-slabs, at its real shape
+        log("bench variant: 512x512x64 slab fused fp64")
+        r = Run((512, 512, 64), "fused", "fp64")
+        vms, _, _ = r.time_steps(40, 2)
+        r.free()
+        variants["fused_fp64_slab_512x512x64"] = {"updates_per_s": r.points * 3 * 40 / (vms * 1e-3),
+                                                  "ms_per_step": vms / 40, "steps": 40}
         f512 = variants["fused_fp64_512"]["updates_per_s"]
         s512 = variants["stored_fp64_512"]["updates_per_s"]
         variants["fused_over_stored_512"] = f512 / s512

@@ -330,6 +330,12 @@ def test_512_sampled_residual_fused(ns):
     _sampled_check(ns, (512, 512, 512), "fused", 1, 2000)
 
 
+def test_slab_512x512x64_sampled_residual_fused(ns):
+    """One GPU's share of a 512^3 grid split into 8 z-slabs, at its real
+    shape (512 x 512 x 64, periodic here instead of exchanging halos)."""
+    _sampled_check(ns, (512, 512, 64), "fused", 2, 2000)
+
+
 def test_256_fused_vs_stored_states_and_conservation(ns):
     """256^3 TGV, 20 steps: the three GPU classes agree element by element
     and mass / momentum are conserved to rounding."""
