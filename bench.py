@@ -426,7 +426,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
-        cpu = cpu_baseline(n, 1)
+        cpu = cpu_baseline(n, 2)
         log(f"bench: cpu baseline {cpu['value']:.3e} updates/s on {cpu['cores']} threads")
 
     out = {
