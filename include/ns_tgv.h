@@ -20,16 +20,19 @@
  *     5*nx*ny*nz doubles in device memory.  Point (i,j,k) is at
  *     (i*hx, j*hy, k*hz), h = length / n.
  *   - Pointers named state, Q, R and work are DEVICE pointers owned by the
- *     caller; the library keeps none of them after returning.  out_host is
- *     a host pointer.
+ *     caller; the library keeps none of them after returning, except a
+ *     batch, which keeps its members' state and work pointers until they
+ *     are removed (ns_batch_add).  out_host is a host pointer.
  *   - stream is a hipStream_t (NULL = the default stream).  Calls are
  *     stream-ordered and asynchronous, except diagnostics(), which waits for
  *     its stream.
  *   - Arguments are validated before anything is enqueued; a failed
  *     validation returns an error and touches no memory.  HIP errors map to
- *     NS_ERR_DEVICE.  No C++ exception crosses this boundary.  The library
- *     allocates no device memory: scratch space is the caller's `work`
- *     buffer of at least ns_workspace_bytes() bytes (256-byte aligned).
+ *     NS_ERR_DEVICE.  No C++ exception crosses this boundary.  The single-
+ *     solve entry points allocate no device memory: scratch space is the
+ *     caller's `work` buffer of at least ns_workspace_bytes() bytes
+ *     (256-byte aligned).  A batch allocates its streams, events and
+ *     diagnostics array once, in ns_batch_create.
  */
 #ifndef NS_TGV_H
 #define NS_TGV_H

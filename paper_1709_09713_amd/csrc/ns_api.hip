@@ -1,5 +1,5 @@
 // ns_api.hip -- the C ABI (include/ns_tgv.h): argument validation,
-// workspace layout and the per-step launch sequence of both algorithm
+// workspace layout and the per-step launch sequence of the three algorithm
 // classes.  Every call validates first and enqueues nothing on failure.
 #include <atomic>
 #include <cmath>
