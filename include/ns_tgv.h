@@ -158,7 +158,7 @@ ns_status diagnostics(const ns_params *p, const double *state,
  * (x, y) column tile of one block: 0 = 32x8, 1 = 16x16, 2 = 64x4,
  * 3 = 32x16, 4 = 16x8, 5 = 32x4, 6 = 16x4, 7 = 8x8 (threads = product, one
  * z column each); zchunk is the number of
- * z planes one block marches through (>= 4; 0 = automatic: the length that
+ * z planes one block marches through (>= 1; 0 = automatic: the length that
  * minimises (rounds of device-resident blocks) x (planes each block
  * marches, chunk + 4 halo planes)).  tile = -1 restores the automatic
  * choice.  For a given tile, residuals and states
@@ -214,7 +214,7 @@ typedef struct {
     double dt;          /* > 0, finite */
     int32_t steps;      /* RK3 steps to run (>= 0) */
     int32_t tile;       /* launch tile as in ns_set_fused_config, -1 = default */
-    int32_t zchunk;     /* z planes per block (>= 4), 0 = default */
+    int32_t zchunk;     /* z planes per block (>= 1), 0 = default */
     double *state;      /* device, 5*N doubles: initial state in, result out */
     void *work;         /* device, >= ns_workspace_bytes(p, NS_ALGO_FUSED, batch
                            precision) bytes, 256-byte aligned */

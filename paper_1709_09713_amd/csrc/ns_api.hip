@@ -38,7 +38,7 @@ Consts make_consts(const ns_params *p)
 }
 
 
-constexpr int kMinZChunk = 4;
+constexpr int kMinZChunk = 1;
 static std::atomic<int> g_tile{-1};
 static std::atomic<int> g_zchunk{0};
 static std::atomic<int> g_order{0};

@@ -135,13 +135,13 @@ def test_fused_config_validation():
     with pytest.raises(ns.NativeError):
         ns.ns_set_fused_config(9, 0)
     with pytest.raises(ns.NativeError):
-        ns.ns_set_fused_config(0, 2)
+        ns.ns_set_fused_config(0, -1)
     p = ns.make_params(64)
     ns.ns_set_fused_config(1, 8)
     assert ns.ns_get_fused_config(p) == (1, 8)
     ns.ns_set_fused_config(-1, 0)
     t, z = ns.ns_get_fused_config(p)
-    assert t in ns.TILES and 4 <= z <= 64
+    assert t in ns.TILES and 1 <= z <= 64
     # the default chunk divides the z extent into chunks of equal length
     p256 = ns.make_params(256)
     t, z = ns.ns_get_fused_config(p256)

@@ -152,7 +152,7 @@ def test_tilings_match_oracle_and_zchunk_is_bitwise(ns):
     try:
         for tile in ns.TILES:
             ref = None
-            for zc in (4, 7, 19):
+            for zc in (1, 2, 3, 7, 19):
                 ns.ns_set_fused_config(tile, zc)
                 got = gpu_rk3(ns, p, ns.NS_ALGO_FUSED, ns.NS_FP64, Q0, 1e-3, 2)
                 R = gpu_residual(ns, p, ns.NS_ALGO_FUSED, Q0)
@@ -180,7 +180,7 @@ def test_fp32_tilings_match_oracle_and_zchunk_is_bitwise(ns):
     try:
         for tile in ns.TILES:
             ref = None
-            for zc in (4, 11):
+            for zc in (1, 4, 11):
                 print(f"fp32 tile {tile} zchunk {zc}", flush=True)
                 ns.ns_set_fused_config(tile, zc)
                 got = gpu_rk3(ns, p, ns.NS_ALGO_FUSED, ns.NS_FP32_STORE, Q0, 1e-3, 3)
