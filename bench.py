@@ -82,20 +82,29 @@ class Run:
         ns.rk3_step(self.p, self.algo, self.prec, self.dt, k, self.state, self.work,
                     diag_dev=diag, stream=self.stream)
 
-    def time_steps(self, k, warmup, with_diag=True):
+    def time_steps(self, k, warmup, with_diag=True, chunks=1):
+        """Time exactly k steps (HIP events on the launch stream, device
+        synchronised on both sides).  With chunks > 1 (dividing k), events
+        are also recorded at the chunk boundaries inside the timed region;
+        the per-chunk times come back in self.chunk_ms."""
         diag = torch.zeros((max(k, warmup, 1), 8), dtype=torch.float64, device="cuda") if with_diag else None
         if warmup:
             self.steps(warmup, diag)
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        if k % chunks:
+            chunks = 1
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(chunks + 1)]
         t0 = time.perf_counter()
-        e0.record(self.stream)
-        self.steps(k, diag)
-        e1.record(self.stream)
+        ev[0].record(self.stream)
+        per = k // chunks
+        for c in range(chunks):
+            d = diag[c * per:] if diag is not None else None
+            self.steps(per, d)
+            ev[c + 1].record(self.stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        ms = e0.elapsed_time(e1)
+        ms = ev[0].elapsed_time(ev[-1])
+        self.chunk_ms = [ev[c].elapsed_time(ev[c + 1]) for c in range(chunks)]
         return ms, wall, diag
 
     def free(self):
@@ -329,11 +338,25 @@ def main():
     n, K, W = args.n, args.steps, args.warmup
     log(f"bench: TGV {n}^3 {args.algo} {args.precision}, steps={K} warmup={W}")
     run = Run(n, args.algo, args.precision)
-    ms, wall, diag = run.time_steps(K, W)
+    ms, wall, diag = run.time_steps(K, W, chunks=5)
     upd = n ** 3 * 3 * K
     value = upd / (ms * 1e-3)
     ms_step = ms / K
-    ke = diag[K - 1, 5].item()
+    chunk_steps = K // len(run.chunk_ms)
+    chunk_ms_step = sorted(c / chunk_steps for c in run.chunk_ms)
+    repeats = {"chunks": len(run.chunk_ms), "steps_each": chunk_steps,
+               "median_ms_per_step": chunk_ms_step[len(chunk_ms_step) // 2],
+               "min_ms_per_step": chunk_ms_step[0], "max_ms_per_step": chunk_ms_step[-1]}
+    d = diag[:K].cpu().numpy()
+    ke = float(d[K - 1, 5])
+    # kinetic-energy budget of the TGV: -dKE/dt from the per-step series
+    # (central difference) beside the dissipation eps = 2 Omega / Re
+    budget = None
+    if K >= 3:
+        dke = -(d[K - 1, 5] - d[K - 3, 5]) / (2.0 * run.dt)
+        eps = float(d[K - 2, 7])
+        budget = {"step": K - 2, "minus_dKE_dt": float(dke), "epsilon": eps,
+                  "ratio": float(dke / eps) if eps else None}
     run.free()
     log(f"bench: {ms_step:.3f} ms/step, {value:.4e} updates/s (wall {wall:.3f} s)")
 
@@ -454,7 +477,9 @@ def main():
         "batched": batch_out,
         "serving": serve_out,
         "energy": energy_out,
+        "repeats": repeats,
         "kinetic_energy_last_step": ke,
+        "tgv_energy_budget": budget,
         "paper_context": "paper (other hardware, 256^3 TGV): best K40c SN2 ~1.14e8, 24-core Ivy "
                          "Bridge SN 4.58e7 updates/s (derived from its runtimes); "
                          "on-the-fly ~2x faster than stored derivatives",
