@@ -117,6 +117,8 @@ class Server:
         """Serve `requests` (dicts with rid, arrival [s from start], n,
         reynolds, mach, dt, steps) in real time; returns (results sorted by
         rid, summary)."""
+        if not requests:
+            return [], {"requests": 0}
         be = self.backend
         stream = be.stream()
         side = be.side_stream()
@@ -202,6 +204,8 @@ class Server:
 def serve_sequential(requests, precision: str = "fp64", keep_states: bool = False):
     """The same requests solved one at a time, first come first served,
     each with one rk3_step call of the fused class."""
+    if not requests:
+        return [], {"requests": 0}
     stream = torch.cuda.current_stream()
     prec = nat.PRECS[precision]
     results = []

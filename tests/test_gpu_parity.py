@@ -407,3 +407,26 @@ def test_fp32_storage_long_run_error_vs_fp64(ns):
     e = rel(got[ns.NS_FP32_STORE], got[ns.NS_FP64])
     print(f"128^3x50 fp32-store vs fp64: rel per field {['%.2e' % x for x in e]}", flush=True)
     assert 1e-12 < max(e) < 1e-5, e
+
+
+@pytest.mark.parametrize("algo", ["fused", "stored", "some"])
+def test_uniform_state_has_zero_residual(ns, algo):
+    """A uniform state (constant rho, velocity and pressure) is a steady
+    solution: every stencil of it vanishes.  First-derivative stencils of
+    equal values are exactly 0; the second-derivative stencil can keep the
+    rounding of 30 f (a multiply-add may skip it), so R is 0 to within a
+    few ulps of the terms, and RK3 steps leave the state unchanged to
+    rounding."""
+    n = (24, 20, 18)
+    Q = np.empty((5, n[2], n[1], n[0]))
+    rho, u = 1.3, (0.2, -0.1, 0.05)
+    p_ = 1.0 / (1.4 * 0.2 ** 2)
+    Q[0] = rho
+    for a in range(3):
+        Q[1 + a] = rho * u[a]
+    Q[4] = p_ / 0.4 + 0.5 * rho * sum(x * x for x in u)
+    p = params(ns, n, mach=0.2)
+    R = gpu_residual(ns, p, ns.ALGOS[algo], Q)
+    assert np.abs(R).max() < 1e-10, np.abs(R).max()
+    got = gpu_rk3(ns, p, ns.ALGOS[algo], ns.NS_FP64, Q, 1e-3, 2)
+    assert np.allclose(got, Q, rtol=1e-14, atol=0.0)

@@ -128,3 +128,8 @@ def test_summary_statistics():
     s = summarize(rs, 0.0, 4.0)
     assert s["p50_latency_s"] == 2.0 and s["mean_latency_s"] == 2.0
     assert s["updates_per_s"] == 3 * 10 ** 3 * 3 * 2 / 4.0
+
+
+def test_no_requests():
+    res, summ = Server("fp32", max_instances=2, backend=FakeBackend(2)).run([])
+    assert res == [] and summ["requests"] == 0
