@@ -430,3 +430,29 @@ def test_uniform_state_has_zero_residual(ns, algo):
     assert np.abs(R).max() < 1e-10, np.abs(R).max()
     got = gpu_rk3(ns, p, ns.ALGOS[algo], ns.NS_FP64, Q, 1e-3, 2)
     assert np.allclose(got, Q, rtol=1e-14, atol=0.0)
+
+
+@pytest.mark.parametrize("algo", ["fused", "stored", "some"])
+def test_residual_is_fourth_order_on_gpu(ns, algo):
+    """Self-convergence of the GPU residual of the Taylor-Green state:
+    grids of 32^3, 64^3 and 128^3 share the points of the coarsest, where
+    the differences R_N - R_2N shrink by 2^4 per refinement (a dropped term
+    or a wrong stencil weight breaks the order)."""
+    R = {}
+    for n in (32, 64, 128):
+        p = params(ns, (n, n, n))
+        Qd = torch.empty((5, n, n, n), dtype=torch.float64, device="cuda")
+        ns.tgv_init(p, Qd)
+        Rd = torch.empty_like(Qd)
+        ns.ns_residual(p, ns.ALGOS[algo], Qd, Rd, work_for(ns, p, ns.ALGOS[algo]))
+        torch.cuda.synchronize()
+        s = n // 32
+        R[n] = Rd[:, ::s, ::s, ::s].cpu().numpy()
+    for f in range(5):
+        e1 = np.abs(R[32][f] - R[64][f]).max()
+        e2 = np.abs(R[64][f] - R[128][f]).max()
+        if e1 < 1e-9:          # the field's residual is zero at t = 0 (rho w)
+            continue
+        ratio = e1 / e2
+        print(f"{algo} field {f}: |R32-R64| {e1:.3e} |R64-R128| {e2:.3e} ratio {ratio:.2f}", flush=True)
+        assert 12.0 < ratio < 20.0, (f, ratio)
