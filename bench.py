@@ -431,8 +431,19 @@ def main():
         from paper_1709_09713_amd.autotune import Autotuner
         tuner = Autotuner()
         if not args.no_batched:
-            log("bench: batched 64 instances")
-            batch_out = batched(tuner)
+            per_seed = []
+            for seed in (0, 1, 2):
+                log(f"bench: batched 64 instances, seed {seed}")
+                per_seed.append(batched(tuner, seed=seed))
+            batch_out = dict(per_seed[0])
+            batch_out["seeds"] = {
+                str(b["seed"]): {"batch_fp32": b["batch_fp32"]["updates_per_s"],
+                                 "batch_fp64": b["batch_fp64"]["updates_per_s"],
+                                 "sequential_fp64": b["sequential_fp64"]["updates_per_s"],
+                                 "ratio": b["batch_fp32_over_sequential_fp64"]}
+                for b in per_seed}
+            batch_out["mean_batch_fp32_over_sequential_fp64"] = (
+                sum(b["batch_fp32_over_sequential_fp64"] for b in per_seed) / len(per_seed))
         if not args.no_serving:
             log(f"bench: serving {args.serve_requests} requests")
             serve_out = serving(tuner, count=args.serve_requests)
