@@ -287,7 +287,7 @@ def serving(tuner, seed=0, count=48, rate=50.0):
     for n in sorted({r["n"] for r in reqs}):
         tuner.lookup(n, "fp32")
     torch.cuda.synchronize()
-    srv = Server("fp32", max_instances=64, nstreams=3, quantum=25, tuner=tuner)
+    srv = Server("fp32", max_instances=4, nstreams=3, quantum=25, tuner=tuner)
     _, s32 = srv.run(reqs)
     log(f"bench serving fp32: p50 {s32['p50_latency_s']:.2f} s p99 {s32['p99_latency_s']:.2f} s "
         f"{s32['updates_per_s']:.3e} updates/s")

@@ -99,7 +99,14 @@ class GpuBackend:
 
 
 class Server:
-    def __init__(self, precision: str = "fp32", max_instances: int = 64,
+    """max_instances is the number of requests advanced together.  Once the
+    members in flight fill the device, more of them only share it and
+    stretch every request's latency, so the default is small: on the
+    32^3..192^3 request mix four concurrent members gave both the lowest
+    latency and the highest throughput (64 members: p50 +50%, throughput
+    -4%)."""
+
+    def __init__(self, precision: str = "fp32", max_instances: int = 4,
                  hbm_budget: int | None = None, nstreams: int = 3, quantum: int = 25,
                  tuner=None, keep_states: bool = False, backend=None):
         self.precision = precision
