@@ -48,7 +48,8 @@ BYTES_PER_POINT_STEP = {"fp64": 400.0, "fp32": 320.0}
 
 # Sources of the fused stage kernel: traffic counters recorded for another
 # version of them are not reported.
-FUSED_SOURCES = ("paper_1709_09713_amd/csrc/ns_fused.hip", "paper_1709_09713_amd/csrc/ns_common.hpp")
+FUSED_SOURCES = ("paper_1709_09713_amd/csrc/ns_fused.hip", "paper_1709_09713_amd/csrc/ns_split.hip",
+                 "paper_1709_09713_amd/csrc/ns_common.hpp")
 
 
 def fused_source_hash():

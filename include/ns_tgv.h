@@ -157,7 +157,9 @@ ns_status diagnostics(const ns_params *p, const double *state,
 /* Launch shape of the fused kernel, process-wide.  tile selects the
  * (x, y) column tile of one block: 0 = 32x8, 1 = 16x16, 2 = 64x4,
  * 3 = 32x16, 4 = 16x8, 5 = 32x4, 6 = 16x4, 7 = 8x8 (threads = product, one
- * z column each); zchunk is the number of
+ * z column each); 8 = 16x8, 9 = 32x8, 10 = 16x4 with two threads per
+ * column (one evaluates the mass and momentum equations, the other the
+ * energy equation and the viscous terms); zchunk is the number of
  * z planes one block marches through (>= 1; 0 = automatic: the length that
  * minimises (rounds of device-resident blocks) x (planes each block
  * marches, chunk + 4 halo planes)).  tile = -1 restores the automatic
@@ -180,7 +182,7 @@ ns_status ns_get_fused_config(const ns_params *p, ns_precision prec,
  * (default); 1 = grouped by derivative direction (all x derivatives of all
  * equations, then all y derivatives).  The two orders sum the same terms
  * with a different association, so results differ at the rounding level
- * only.  Order 1 is compiled for tiles 16x8 and 32x8 only: rk3_step,
+ * only.  Order 1 is compiled for tiles 4 (16x8) and 0 (32x8) only: rk3_step,
  * ns_residual and ns_batch_add return NS_ERR_UNSUPPORTED for it with any
  * other tile.  NS_ERR_ARG for other values. */
 ns_status ns_set_fused_order(int32_t order);

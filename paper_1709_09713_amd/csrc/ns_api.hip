@@ -43,8 +43,8 @@ static std::atomic<int> g_tile{-1};
 static std::atomic<int> g_zchunk{0};
 static std::atomic<int> g_order{0};
 
-// Default z-chunk: a block marches zchunk + 4 planes (padded to the unroll
-// of 5), and the grid runs in ceil(blocks / resident) rounds of resident
+// Default z-chunk: a block marches zchunk + 4 planes (+ 5 for the
+// two-group tiles; padded to the unroll of 5), and the grid runs in ceil(blocks / resident) rounds of resident
 // blocks, so the time of a stage goes as rounds x padded planes.  Pick the
 // number of chunks along z that minimises it (fewest blocks on a tie).
 // resident = blocks the device holds at once (512 on MI355X for the default
@@ -63,7 +63,7 @@ static int default_zchunk(const Consts &c, ns_precision prec, int tile)
         const int chunks = (c.nz + z - 1) / z;
         if (chunks != k) continue;   // the same z as a smaller k
         const int64_t rounds = (chunks * nxy + resident - 1) / resident;
-        const int64_t planes = ((z + 4 + 4) / 5) * 5;
+        const int64_t planes = ((z + fused_extra_planes(tile) + 4) / 5) * 5;
         const int64_t cost = rounds * planes;
         if (best_cost < 0 || cost < best_cost) {
             best_cost = cost;
@@ -81,7 +81,10 @@ static void choose_config(const Consts &c, ns_precision prec, int tile_in, int z
     int t = tile_in >= 0 ? tile_in : g_tile.load();
     int z = tile_in >= 0 ? zchunk_in : g_zchunk.load();
     if (zchunk_in > 0) z = zchunk_in;
-    if (t < 0 || t >= TILE_COUNT) t = (prec == NS_FP64) ? TILE_16x8 : TILE_32x8;
+    // defaults measured on MI355X: FP64 runs fastest with the two-group
+    // 32x8 kernel at every cube from 128^3 to 512^3, FP32 storage with the
+    // one-thread 32x8 kernel
+    if (t < 0 || t >= TILE_COUNT) t = (prec == NS_FP64) ? TILE_32x8_2G : TILE_32x8;
     if (z <= 0) z = default_zchunk(c, prec, t);
     if (z < kMinZChunk) z = kMinZChunk;
     if (z > c.nz) z = c.nz;

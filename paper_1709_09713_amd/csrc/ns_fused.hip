@@ -590,6 +590,8 @@ void tile_dims(int tile, int *bx, int *by)
     case TILE_32x4: *bx = 32; *by = 4; break;
     case TILE_16x4: *bx = 16; *by = 4; break;
     case TILE_8x8: *bx = 8; *by = 8; break;
+    case TILE_16x8_2G: *bx = 16; *by = 8; break;
+    case TILE_16x4_2G: *bx = 16; *by = 4; break;
     default: *bx = 32; *by = 8; break;
     }
 }
@@ -636,8 +638,11 @@ int fused_resident_blocks(ns_precision prec, int tile)
     const int q = prec == NS_FP64 ? 0 : 1;
     int r = cache[dev][q][tile].load();
     if (r == 0) {
-        r = prec == NS_FP64 ? resident_tile<double, double, double>(tile)
-                            : resident_tile<float, float, float>(tile);
+        if (split_tile(tile))
+            r = split_resident_blocks(prec, tile);
+        else
+            r = prec == NS_FP64 ? resident_tile<double, double, double>(tile)
+                                : resident_tile<float, float, float>(tile);
         if (r > 0) cache[dev][q][tile].store(r);
     }
     return r;
@@ -647,6 +652,8 @@ bool fused_order_supported(int tile, int order)
 {
     return order == 0 || (order == 1 && (tile == TILE_16x8 || tile == TILE_32x8));
 }
+
+int fused_extra_planes(int tile) { return split_tile(tile) ? 5 : 4; }
 
 int64_t fused_num_blocks(const Consts &c, int tile, int zchunk)
 {
@@ -658,6 +665,7 @@ int64_t fused_num_blocks(const Consts &c, int tile, int zchunk)
 hipError_t launch_fused_stage(const Consts &c, const StageArgs &s, ns_precision prec,
                               int tile, hipStream_t st)
 {
+    if (split_tile(tile)) return launch_split_stage(c, s, prec, tile, st);
     if (prec == NS_FP64)
         return launch_tile<double, double, double>(tile, c, s, st);
     // FP32 storage: stage 1 reads the double state, stage 3 writes it.

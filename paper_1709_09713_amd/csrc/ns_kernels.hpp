@@ -5,11 +5,15 @@
 
 namespace ns {
 
-// Column-tile shapes of the fused kernel (threads = BX * BY, one z column
-// each).  Chosen per problem by the autotuner or by the default rule.
+// Column-tile shapes of the fused kernel.  Tiles 0-7: threads = BX * BY,
+// one z column each (ns_fused.hip).  Tiles 8-10 (_2G): 2 * BX * BY
+// threads, two per column, the mass/momentum and the energy equations
+// split between two wave groups (ns_split.hip).  Chosen per problem by the
+// autotuner or by the default rule.
 enum {
     TILE_32x8 = 0, TILE_16x16 = 1, TILE_64x4 = 2, TILE_32x16 = 3,
-    TILE_16x8 = 4, TILE_32x4 = 5, TILE_16x4 = 6, TILE_8x8 = 7, TILE_COUNT = 8
+    TILE_16x8 = 4, TILE_32x4 = 5, TILE_16x4 = 6, TILE_8x8 = 7,
+    TILE_16x8_2G = 8, TILE_32x8_2G = 9, TILE_16x4_2G = 10, TILE_COUNT = 11
 };
 
 // One fused launch: residual only (mode 0) or RK stage 1..3.
@@ -34,6 +38,13 @@ bool fused_order_supported(int tile, int order);
 int fused_resident_blocks(ns_precision prec, int tile);
 hipError_t launch_fused_stage(const Consts &c, const StageArgs &s, ns_precision prec,
                               int tile, hipStream_t st);
+// The two-group kernel (tiles 8-10): stage launch and resident blocks.
+bool split_tile(int tile);
+int split_resident_blocks(ns_precision prec, int tile);
+hipError_t launch_split_stage(const Consts &c, const StageArgs &s, ns_precision prec, int tile,
+                              hipStream_t st);
+// Planes a block marches beyond its chunk (halo and pipeline depth).
+int fused_extra_planes(int tile);
 
 // A validated fused-class RK3 plan for one solve: constants, launch shape
 // and the carve-up of its workspace.  rk3_step and the batch scheduler

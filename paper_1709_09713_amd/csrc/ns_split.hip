@@ -1,0 +1,611 @@
+// ns_split.hip -- the fused on-the-fly stage kernel with the work of each
+// grid point split between two groups of waves.
+//
+// Same algorithm class and arithmetic as the one-thread-per-column kernel of
+// ns_fused.hip (minimal storage: every derivative of the governing-equations
+// section evaluated on the fly from an LDS-staged (x, y) tile marching along
+// z, the low-storage RK3 update of the generic-algorithm figure in the same
+// pass), but a block holds two threads per column of its tile:
+//  * group M (threads [0, NT)) loads and stages each plane into LDS and
+//    evaluates the mass and momentum equations;
+//  * group E (threads [NT, 2 NT)) evaluates the energy equation and the
+//    viscous vector V_i = lap u_i + (1/3) d_i div u, which the momentum
+//    equations need too.  E hands V to M through a small LDS buffer: in the
+//    step of plane zp it writes the in-plane part of V at plane zp and the
+//    z part at plane zp - 2, and M reads both one step later, after the
+//    plane barrier.  So M finishes plane zp - 3 in that step, one plane
+//    behind E.
+// Each group keeps only its own equations' z-ring state, about half of the
+// one-thread kernel's ring registers, so a block of 2 NT threads fits where
+// NT threads of the one-thread kernel did not leave room for a second wave
+// per SIMD, and the two groups' instruction streams hide each other's LDS
+// and memory latency.
+//
+// The z-derivative handling (constant-coefficient fluxes scattered into a
+// five-deep ring of pending residuals, point-value-weighted terms gathered
+// from a ring of primitives, mixed derivatives as z derivatives of in-plane
+// ones), the FP32 deviation storage format and the diagnostics of the stage
+// input follow the one-thread kernel.
+#include <type_traits>
+
+#include "ns_common.hpp"
+#include "ns_kernels.hpp"
+
+namespace ns {
+
+namespace {
+
+template <typename TIN, typename CT>
+__device__ __forceinline__ CT sp_to_ct(TIN v, double ref)
+{
+    if constexpr (std::is_same<CT, double>::value)
+        return v;
+    else if constexpr (std::is_same<TIN, double>::value)
+        return (float)(v - ref);
+    else
+        return v;
+}
+
+// Stage outputs and the accumulator are touched once per stage: streamed
+// past L2 so they do not displace the input planes that neighbouring blocks
+// read again as halo.
+template <typename TOUT>
+__device__ __forceinline__ void sp_store(void *q, int64_t i, double v, double ref)
+{
+    if constexpr (std::is_same<TOUT, double>::value)
+        __builtin_nontemporal_store(v, (double *)q + i);
+    else
+        __builtin_nontemporal_store((float)(v - ref), (float *)q + i);
+}
+
+// 1/x: hardware estimate and Newton steps r <- r + r (1 - x r); two steps
+// reach double rounding error, one single.  x (a density) is positive and
+// normal.
+__device__ __forceinline__ double sp_recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float sp_recip(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    const float e = __builtin_fmaf(-x, r, 1.0f);
+    return __builtin_fmaf(r, e, r);
+}
+
+template <int V>
+using SIC = std::integral_constant<int, V>;
+
+}  // namespace
+
+template <int BX, int BY, typename TIN, typename TOUT, typename CT, bool DIAG>
+__global__ void __launch_bounds__(2 * BX * BY)
+split_stage_kernel(Consts c, StageArgs s)
+{
+    constexpr bool DEV = std::is_same<CT, float>::value;
+    constexpr int HX = BX + 4, HY = BY + 4, HP = HX * HY, NT = BX * BY;
+    constexpr int NLOAD = (HP + NT - 1) / NT;
+    constexpr int NW = 2 * NT / 64;
+    static_assert(NT % 64 == 0, "each group must be whole waves");
+    enum { L_RHO, L_M0, L_M1, L_M2, L_E, L_U, L_V, L_W, L_P, L_T, NF };
+    __shared__ CT lds[2][NF][HP];
+    // E -> M: (V_x, V_y, V_z) in-plane part at plane zp, z part at plane zp - 2
+    __shared__ CT vbuf[2][6][NT];
+    __shared__ double red[NW][kDiag];
+
+    // The group is a property of the wave; reading it through a scalar
+    // register makes the branch below a scalar branch, so each wave runs
+    // exactly one group's march (and its barriers).
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const bool grp_e = wave >= NT / 64;
+    const int pt = (int)threadIdx.x - (grp_e ? NT : 0);
+    const int tx = pt % BX, ty = pt / BX;
+    int tbx, tby, tbz;
+    xcd_tile(&tbx, &tby, &tbz);
+    const int x0 = tbx * BX, y0 = tby * BY;
+    const int z0 = tbz * s.zchunk;
+    const int z1 = min(z0 + s.zchunk, c.nz);
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool active = (gx < c.nx) && (gy < c.ny);
+    const int own = (ty + 2) * HX + tx + 2;
+    const int64_t N = c.N;
+    const int64_t col = active ? (int64_t)gy * c.nx + gx : 0;
+
+    const CT c1x = (CT)c.c1[0], c1y = (CT)c.c1[1], c1z = (CT)c.c1[2];
+    const CT c2x = (CT)c.c2[0], c2y = (CT)c.c2[1], c2z = (CT)c.c2[2];
+    const CT inv_re = (CT)c.inv_re, kappa = (CT)c.kappa;
+    const CT gm1 = (CT)c.gm1, gM2 = (CT)c.gM2;
+    const CT half = CT(0.5), third = CT(1) / CT(3), four3 = CT(4) / CT(3);
+    const CT two3 = CT(2) / CT(3);
+    const CT kz = kappa * c2z;
+
+    double dsum[DIAG ? 7 : 1];
+#pragma unroll
+    for (int k = 0; k < (DIAG ? 7 : 1); ++k) dsum[k] = 0.0;
+
+    // The march covers planes z0-2 .. z1+2 (M finishes a plane three steps
+    // after loading it), padded to a multiple of 5; padding planes are
+    // loaded (wrapped, valid memory) but never output.
+    const int L = z1 - z0 + 5;
+
+#define LV(f, dy, dx) lds[b][f][own + (dy) * HX + (dx)]
+#define DX1(f) d1u(LV(f, 0, -2), LV(f, 0, -1), LV(f, 0, 1), LV(f, 0, 2))
+#define DY1(f) d1u(LV(f, -2, 0), LV(f, -1, 0), LV(f, 1, 0), LV(f, 2, 0))
+#define DX1P(f, g)                                                       \
+    d1u(LV(f, 0, -2) * LV(g, 0, -2), LV(f, 0, -1) * LV(g, 0, -1),        \
+        LV(f, 0, 1) * LV(g, 0, 1), LV(f, 0, 2) * LV(g, 0, 2))
+#define DY1P(f, g)                                                       \
+    d1u(LV(f, -2, 0) * LV(g, -2, 0), LV(f, -1, 0) * LV(g, -1, 0),        \
+        LV(f, 1, 0) * LV(g, 1, 0), LV(f, 2, 0) * LV(g, 2, 0))
+#define HF(dy, dx, g) ((half * LV(L_E, dy, dx) + LV(L_P, dy, dx)) * LV(g, dy, dx))
+#define DX1H() d1u(HF(0, -2, L_U), HF(0, -1, L_U), HF(0, 1, L_U), HF(0, 2, L_U))
+#define DY1H() d1u(HF(-2, 0, L_V), HF(-1, 0, L_V), HF(1, 0, L_V), HF(2, 0, L_V))
+#define DX2(f) d2u(LV(f, 0, -2), LV(f, 0, -1), LV(f, 0, 0), LV(f, 0, 1), LV(f, 0, 2))
+#define DY2(f) d2u(LV(f, -2, 0), LV(f, -1, 0), LV(f, 0, 0), LV(f, 1, 0), LV(f, 2, 0))
+#define DXDY(f)                                                          \
+    d1u(d1u(LV(f, -2, -2), LV(f, -1, -2), LV(f, 1, -2), LV(f, 2, -2)),   \
+        d1u(LV(f, -2, -1), LV(f, -1, -1), LV(f, 1, -1), LV(f, 2, -1)),   \
+        d1u(LV(f, -2, 1), LV(f, -1, 1), LV(f, 1, 1), LV(f, 2, 1)),       \
+        d1u(LV(f, -2, 2), LV(f, -1, 2), LV(f, 1, 2), LV(f, 2, 2)))
+#define DYDX(f)                                                          \
+    d1u(d1u(LV(f, -2, -2), LV(f, -2, -1), LV(f, -2, 1), LV(f, -2, 2)),   \
+        d1u(LV(f, -1, -2), LV(f, -1, -1), LV(f, -1, 1), LV(f, -1, 2)),   \
+        d1u(LV(f, 1, -2), LV(f, 1, -1), LV(f, 1, 1), LV(f, 1, 2)),       \
+        d1u(LV(f, 2, -2), LV(f, 2, -1), LV(f, 2, 1), LV(f, 2, 2)))
+
+    if (!grp_e) {
+        // ------------------------------------------------------------ group M
+        const TIN *qin = (const TIN *)s.qin;
+        enum { Z_RHO, Z_U, Z_V, Z_W, NZ };
+        CT qz[5][NZ];      // ring: rho, u, v, w of the own column
+        CT ra[5][4];       // ring: pending mass and momentum residuals
+        CT rp[4];          // plane zp - 2 with its z terms, V still missing
+        TIN pf[NLOAD][5];  // next plane, prefetched
+        double acc[4];
+#pragma unroll
+        for (int q = 0; q < 5; ++q)
+#pragma unroll
+            for (int f = 0; f < 4; ++f) qz[q][f] = ra[q][f] = CT(0);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) rp[f] = CT(0);
+
+        int loff[NLOAD];
+#pragma unroll
+        for (int r = 0; r < NLOAD; ++r) {
+            const int idx = pt + r * NT;
+            loff[r] = 0;
+            if (idx < HP) {
+                const int lx = idx % HX, ly = idx / HX;
+                int xx = (x0 + lx - 2) % c.nx;
+                if (xx < 0) xx += c.nx;
+                int yy = (y0 + ly - 2) % c.ny;
+                if (yy < 0) yy += c.ny;
+                loff[r] = yy * c.nx + xx;
+            }
+        }
+        auto load_plane = [&](int zp) {
+            int zw = zp % c.nz;
+            if (zw < 0) zw += c.nz;
+            const int64_t base = (int64_t)zw * c.nxy;
+#pragma unroll
+            for (int r = 0; r < NLOAD; ++r) {
+                const int64_t g = base + loff[r];
+#pragma unroll
+                for (int f = 0; f < 5; ++f) pf[r][f] = qin[g + f * N];
+            }
+        };
+        auto stage_plane = [&](int b) {
+#pragma unroll
+            for (int r = 0; r < NLOAD; ++r) {
+                const int idx = pt + r * NT;
+                if (idx < HP) {
+                    const CT rho = sp_to_ct<TIN, CT>(pf[r][0], c.rho_ref);
+                    const CT m0 = sp_to_ct<TIN, CT>(pf[r][1], 0.0);
+                    const CT m1 = sp_to_ct<TIN, CT>(pf[r][2], 0.0);
+                    const CT m2 = sp_to_ct<TIN, CT>(pf[r][3], 0.0);
+                    const CT E = sp_to_ct<TIN, CT>(pf[r][4], c.rhoE_ref);
+                    const CT rhof = DEV ? CT(1) + rho : rho;
+                    const CT inv = sp_recip(rhof);
+                    const CT u = m0 * inv, v = m1 * inv, w = m2 * inv;
+                    const CT p = gm1 * (E - half * (m0 * u + m1 * v + m2 * w));
+                    const CT T = DEV ? (gM2 * p - rho) * inv : gM2 * p * inv;
+                    lds[b][L_RHO][idx] = rho;
+                    lds[b][L_M0][idx] = m0;
+                    lds[b][L_M1][idx] = m1;
+                    lds[b][L_M2][idx] = m2;
+                    lds[b][L_E][idx] = E;
+                    lds[b][L_U][idx] = u;
+                    lds[b][L_V][idx] = v;
+                    lds[b][L_W][idx] = w;
+                    lds[b][L_P][idx] = p;
+                    lds[b][L_T][idx] = T;
+                }
+            }
+        };
+
+        auto step = [&](auto phc, int zp) {
+            constexpr int PH = decltype(phc)::value;
+            constexpr int SM2 = (PH + 3) % 5, SM1 = (PH + 4) % 5, S0 = PH;
+            constexpr int SP1 = (PH + 1) % 5, SP2 = (PH + 2) % 5;
+            constexpr int SM4 = (PH + 1) % 5, SM3 = (PH + 2) % 5;
+            const int b = (zp - z0) & 1;
+            const int zf = zp - 3;
+            const bool fin = active && zf >= z0 && zf < z1;
+            {
+                // accumulator (stages 2, 3) or exact input state of the
+                // point finished in this step; idle threads read a valid
+                // address they ignore
+                const double *src = (s.mode >= 2) ? s.acc_in : (const double *)s.qin;
+                const int64_t pidx = (int64_t)(fin ? zf : z0) * c.nxy + col;
+#pragma unroll
+                for (int f = 0; f < 4; ++f) acc[f] = __builtin_nontemporal_load(src + f * N + pidx);
+            }
+            load_plane(zp + 1);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) ra[SP2][f] = CT(0);
+
+            if (active) {
+                const CT rho = LV(L_RHO, 0, 0);
+                const CT m0 = LV(L_M0, 0, 0), m1 = LV(L_M1, 0, 0), m2 = LV(L_M2, 0, 0);
+                const CT u = LV(L_U, 0, 0), v = LV(L_V, 0, 0), w = LV(L_W, 0, 0);
+                const CT p = LV(L_P, 0, 0);
+                qz[S0][Z_RHO] = rho;
+                qz[S0][Z_U] = u;
+                qz[S0][Z_V] = v;
+                qz[S0][Z_W] = w;
+
+                const CT g0 = -half * c1z * m2;                  // -1/2 d(rho w)/dz
+                const CT g1 = -half * c1z * (m0 * w);            // -1/2 d(rho u w)/dz
+                const CT g2 = -half * c1z * (m1 * w);            // -1/2 d(rho v w)/dz
+                const CT g3 = -c1z * (half * (m2 * w) + p);      // -1/2 d(rho w w)/dz - dp/dz
+                const CT g[4] = {g0, g1, g2, g3};
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    ra[SM2][f] -= g[f];
+                    ra[SM1][f] += CT(8) * g[f];
+                    ra[SP1][f] -= CT(8) * g[f];
+                    ra[SP2][f] += g[f];
+                }
+
+                if (zp >= z0 && zp < z1) {
+                    const CT rhof = DEV ? CT(1) + rho : rho;
+                    const CT uc = u * c1x, vc = v * c1y;
+                    const CT a = c1x * DX1(L_U) + c1y * DY1(L_V);
+                    ra[S0][0] -= half * (c1x * DX1(L_M0) + c1y * DY1(L_M1) + rhof * a
+                                         + uc * DX1(L_RHO) + vc * DY1(L_RHO));
+                    ra[S0][1] -= half * (c1x * DX1P(L_M0, L_U) + c1y * DY1P(L_M0, L_V) + m0 * a
+                                         + uc * DX1(L_M0) + vc * DY1(L_M0))
+                                 + c1x * DX1(L_P);
+                    ra[S0][2] -= half * (c1x * DX1P(L_M1, L_U) + c1y * DY1P(L_M1, L_V) + m1 * a
+                                         + uc * DX1(L_M1) + vc * DY1(L_M1))
+                                 + c1y * DY1(L_P);
+                    ra[S0][3] -= half * (c1x * DX1P(L_M2, L_U) + c1y * DY1P(L_M2, L_V) + m2 * a
+                                         + uc * DX1(L_M2) + vc * DY1(L_M2));
+                }
+                // in-plane viscous part of plane zp - 1 (from E's last step)
+                if (zp - 1 >= z0 && zp - 1 < z1) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) ra[SM1][1 + k] += inv_re * vbuf[b ^ 1][k][pt];
+                }
+            }
+
+            // stage plane zp + 1 into the other LDS buffer (last read in the
+            // previous step, before its barrier)
+            stage_plane(b ^ 1);
+
+            // finish plane zp - 3: z viscous part from E, RK update, output
+            if (fin) {
+                double Rd[4];
+                Rd[0] = (double)rp[0];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) Rd[1 + k] = (double)(rp[1 + k] + inv_re * vbuf[b ^ 1][3 + k][pt]);
+                const int64_t pidx = (int64_t)zf * c.nxy + col;
+                if (s.mode == 0) {
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) s.rout[f * N + pidx] = Rd[f];
+                } else {
+                    if constexpr (DIAG) {
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) dsum[f] += acc[f];
+                        dsum[5] += 0.5 * (acc[1] * (double)qz[SM3][Z_U] + acc[2] * (double)qz[SM3][Z_V]
+                                          + acc[3] * (double)qz[SM3][Z_W]);
+                    }
+                    const double ref[4] = {c.rho_ref, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) {
+                        sp_store<TOUT>(s.qout, f * N + pidx, acc[f] + s.a_dt * Rd[f], ref[f]);
+                        if (s.mode < 3)
+                            __builtin_nontemporal_store(acc[f] + s.b_dt * Rd[f], s.acc_out + f * N + pidx);
+                    }
+                }
+            }
+
+            // gathered z terms of plane zp - 2 (finished in the next step)
+            if (active) {
+#define DZ1(f) d1u(qz[SM4][f], qz[SM3][f], qz[SM1][f], qz[S0][f])
+                const CT rho = qz[SM2][Z_RHO];
+                const CT u = qz[SM2][Z_U], v = qz[SM2][Z_V], w = qz[SM2][Z_W];
+                const CT rhof = DEV ? CT(1) + rho : rho;
+                const CT wc = w * c1z;
+                const CT Gzz = c1z * DZ1(Z_W);
+                rp[0] = ra[SM2][0] - half * (rhof * Gzz + wc * DZ1(Z_RHO));
+                // rho u_i at the z taps (in the deviation form rho is 1 + rho')
+#define RHOF(q) (DEV ? CT(1) + qz[q][Z_RHO] : qz[q][Z_RHO])
+#define DZM(k)                                                                       \
+    d1u(RHOF(SM4) * qz[SM4][k], RHOF(SM3) * qz[SM3][k], RHOF(SM1) * qz[SM1][k],      \
+        RHOF(S0) * qz[S0][k])
+                rp[1] = ra[SM2][1] - half * (rhof * u * Gzz + wc * DZM(Z_U));
+                rp[2] = ra[SM2][2] - half * (rhof * v * Gzz + wc * DZM(Z_V));
+                rp[3] = ra[SM2][3] - half * (rhof * w * Gzz + wc * DZM(Z_W));
+#undef DZM
+#undef RHOF
+#undef DZ1
+            }
+            lds_barrier();
+        };
+
+        // prologue: plane z0 - 2 into LDS buffer 0
+        load_plane(z0 - 2);
+        stage_plane(0);
+        lds_barrier();
+        for (int it = 0; it < L; it += 5) {
+            const int zp = z0 - 2 + it;
+            step(SIC<0>{}, zp);
+            step(SIC<1>{}, zp + 1);
+            step(SIC<2>{}, zp + 2);
+            step(SIC<3>{}, zp + 3);
+            step(SIC<4>{}, zp + 4);
+        }
+    } else {
+        // ------------------------------------------------------------ group E
+        constexpr int NZ = DIAG ? 5 : 4;
+        enum { Z_E, Z_U, Z_V, Z_W, Z_RHO };
+        constexpr int NR = DIAG ? 2 : 1;
+        CT qz[5][NZ];               // ring: rho E, u, v, w (+ rho) of the own column
+        CT qa[5], qb[5], qc[5];     // ring: D_x u + D_y v, D_x w, D_y w
+        CT ra[5][NR];               // ring: pending energy residual (+ omega_z)
+        double acc4;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            qa[q] = qb[q] = qc[q] = CT(0);
+#pragma unroll
+            for (int f = 0; f < NZ; ++f) qz[q][f] = CT(0);
+#pragma unroll
+            for (int f = 0; f < NR; ++f) ra[q][f] = CT(0);
+        }
+
+        auto step = [&](auto phc, int zp) {
+            constexpr int PH = decltype(phc)::value;
+            constexpr int SM2 = (PH + 3) % 5, SM1 = (PH + 4) % 5, S0 = PH;
+            constexpr int SP1 = (PH + 1) % 5, SP2 = (PH + 2) % 5;
+            constexpr int SM4 = (PH + 1) % 5, SM3 = (PH + 2) % 5;
+            const int b = (zp - z0) & 1;
+            const int zf = zp - 2;
+            const bool fin = active && zf >= z0 && zf < z1;
+            {
+                const double *src = (s.mode >= 2) ? s.acc_in : (const double *)s.qin;
+                const int64_t pidx = (int64_t)(fin ? zf : z0) * c.nxy + col;
+                acc4 = __builtin_nontemporal_load(src + 4 * N + pidx);
+            }
+#pragma unroll
+            for (int f = 0; f < NR; ++f) ra[SP2][f] = CT(0);
+
+            if (active) {
+                const CT E = LV(L_E, 0, 0);
+                const CT u = LV(L_U, 0, 0), v = LV(L_V, 0, 0), w = LV(L_W, 0, 0);
+                const CT p = LV(L_P, 0, 0), T = LV(L_T, 0, 0);
+                const CT Gxx = c1x * DX1(L_U), Gxy = c1y * DY1(L_U);
+                const CT Gyx = c1x * DX1(L_V), Gyy = c1y * DY1(L_V);
+                const CT Gzx = c1x * DX1(L_W), Gzy = c1y * DY1(L_W);
+                const CT a = Gxx + Gyy;
+                qz[S0][Z_E] = E;
+                qz[S0][Z_U] = u;
+                qz[S0][Z_V] = v;
+                qz[S0][Z_W] = w;
+                if constexpr (DIAG) qz[S0][NZ - 1] = LV(L_RHO, 0, 0);
+                qa[S0] = a;
+                qb[S0] = Gzx;
+                qc[S0] = Gzy;
+
+                const CT g4 = -c1z * ((half * E + p) * w);   // -1/2 d(rhoE w)/dz - d(p w)/dz
+                const CT gT = kz * T;                        // kappa d2T/dz2
+                ra[SM2][0] -= g4;
+                ra[SM1][0] += CT(8) * g4;
+                ra[SP1][0] -= CT(8) * g4;
+                ra[SP2][0] += g4;
+                ra[SM2][0] -= gT;
+                ra[SM1][0] += CT(16) * gT;
+                ra[S0][0] -= CT(30) * gT;
+                ra[SP1][0] += CT(16) * gT;
+                ra[SP2][0] -= gT;
+
+                if (zp >= z0 && zp < z1) {
+                    const CT uc = u * c1x, vc = v * c1y;
+                    // d_j tau_ij = lap u_i + (1/3) d_i div u, in-plane parts
+                    const CT Vx = four3 * (c2x * DX2(L_U)) + c2y * DY2(L_U)
+                                  + third * (c1x * c1y * DXDY(L_V));
+                    const CT Vy = c2x * DX2(L_V) + four3 * (c2y * DY2(L_V))
+                                  + third * (c1x * c1y * DYDX(L_U));
+                    const CT Vz = c2x * DX2(L_W) + c2y * DY2(L_W);
+                    vbuf[b][0][pt] = Vx;
+                    vbuf[b][1][pt] = Vy;
+                    vbuf[b][2][pt] = Vz;
+                    // tau_ij du_i/dx_j restricted to terms without a z derivative
+                    const CT phi = CT(2) * (Gxx * Gxx + Gyy * Gyy) + Gxy * Gxy + Gyx * Gyx
+                                   + CT(2) * Gxy * Gyx + Gzx * Gzx + Gzy * Gzy;
+                    ra[S0][0] += -(c1x * DX1H() + c1y * DY1H())
+                                 - half * (E * a + uc * DX1(L_E) + vc * DY1(L_E))
+                                 + inv_re * (u * Vx + v * Vy + w * Vz + phi)
+                                 + kappa * (c2x * DX2(L_T) + c2y * DY2(L_T));
+                    if constexpr (DIAG) ra[S0][NR - 1] = Gyx - Gxy;   // omega_z
+                }
+            }
+
+            // finish plane zf = zp - 2: gathered z terms, RK update, output
+            if (fin) {
+#define DZ1(f) d1u(qz[SM4][f], qz[SM3][f], qz[SM1][f], qz[S0][f])
+#define DZ2(f) d2u(qz[SM4][f], qz[SM3][f], qz[SM2][f], qz[SM1][f], qz[S0][f])
+                const CT E = qz[SM2][Z_E];
+                const CT u = qz[SM2][Z_U], v = qz[SM2][Z_V], w = qz[SM2][Z_W];
+                const CT a = qa[SM2], bb = qb[SM2], cc = qc[SM2];
+                const CT wc = w * c1z;
+                const CT Gxz = c1z * DZ1(Z_U), Gyz = c1z * DZ1(Z_V), Gzz = c1z * DZ1(Z_W);
+                const CT Da = c1z * d1u(qa[SM4], qa[SM3], qa[SM1], qa[S0]);
+                const CT Db = c1z * d1u(qb[SM4], qb[SM3], qb[SM1], qb[S0]);
+                const CT Dc = c1z * d1u(qc[SM4], qc[SM3], qc[SM1], qc[S0]);
+                const CT Vx = c2z * DZ2(Z_U) + third * Db;
+                const CT Vy = c2z * DZ2(Z_V) + third * Dc;
+                const CT Vz = four3 * (c2z * DZ2(Z_W)) + third * Da;
+                vbuf[b][3][pt] = Vx;
+                vbuf[b][4][pt] = Vy;
+                vbuf[b][5][pt] = Vz;
+                const CT div = a + Gzz;
+                const CT phi = Gxz * Gxz + Gyz * Gyz + CT(2) * Gzz * Gzz
+                               + CT(2) * (Gxz * bb + Gyz * cc) - two3 * div * div;
+                const CT R4 = ra[SM2][0] - half * (E * Gzz + wc * DZ1(Z_E))
+                              + inv_re * (u * Vx + v * Vy + w * Vz + phi);
+#undef DZ1
+#undef DZ2
+                double Rd4 = (double)R4;
+                if constexpr (DEV) Rd4 -= c.H_ref * ((double)a + (double)Gzz);
+                const int64_t pidx = (int64_t)zf * c.nxy + col;
+                if (s.mode == 0) {
+                    s.rout[4 * N + pidx] = Rd4;
+                } else {
+                    if constexpr (DIAG) {
+                        const CT rho = qz[SM2][NZ - 1];
+                        const CT rhof = DEV ? CT(1) + rho : rho;
+                        const CT ox = cc - Gyz, oy = Gxz - bb, oz = ra[SM2][NR - 1];
+                        dsum[4] += acc4;
+                        dsum[6] += 0.5 * (double)rhof * ((double)ox * (double)ox + (double)oy * (double)oy
+                                                         + (double)oz * (double)oz);
+                    }
+                    sp_store<TOUT>(s.qout, 4 * N + pidx, acc4 + s.a_dt * Rd4, c.rhoE_ref);
+                    if (s.mode < 3)
+                        __builtin_nontemporal_store(acc4 + s.b_dt * Rd4, s.acc_out + 4 * N + pidx);
+                }
+            }
+            lds_barrier();
+        };
+
+        // prologue: matches group M's barrier
+        lds_barrier();
+        for (int it = 0; it < L; it += 5) {
+            const int zp = z0 - 2 + it;
+            step(SIC<0>{}, zp);
+            step(SIC<1>{}, zp + 1);
+            step(SIC<2>{}, zp + 2);
+            step(SIC<3>{}, zp + 3);
+            step(SIC<4>{}, zp + 4);
+        }
+    }
+#undef LV
+#undef DX1
+#undef DY1
+#undef DX1P
+#undef DY1P
+#undef HF
+#undef DX1H
+#undef DY1H
+#undef DX2
+#undef DY2
+#undef DXDY
+#undef DYDX
+
+    if constexpr (DIAG) {
+        // block reduction of the diagnostic partial sums, fixed order
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            double vsum = dsum[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) vsum += __shfl_xor(vsum, off, 64);
+            dsum[k] = vsum;
+        }
+        if ((tid & 63) == 0) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) red[tid >> 6][k] = dsum[k];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const int64_t blin = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            for (int k = 0; k < 7; ++k) {
+                double t = 0.0;
+                for (int wv = 0; wv < NW; ++wv) t += red[wv][k];
+                s.diag_partial[blin * kDiag + k] = t;
+            }
+            s.diag_partial[blin * kDiag + 7] = 0.0;
+        }
+    }
+}
+
+namespace {
+
+template <int BX, int BY, typename TIN, typename TOUT, typename CT>
+hipError_t launch_sp(const Consts &c, const StageArgs &s, hipStream_t st)
+{
+    dim3 block(2 * BX * BY, 1, 1);
+    dim3 grid((c.nx + BX - 1) / BX, (c.ny + BY - 1) / BY, (c.nz + s.zchunk - 1) / s.zchunk);
+    if constexpr (std::is_same<TIN, double>::value) {
+        if (s.diag_partial != nullptr && s.mode == 1) {
+            hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, true>), grid, block, 0, st, c, s);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, false>), grid, block, 0, st, c, s);
+    return hipGetLastError();
+}
+
+template <typename TIN, typename TOUT, typename CT>
+hipError_t launch_sp_tile(int tile, const Consts &c, const StageArgs &s, hipStream_t st)
+{
+    switch (tile) {
+    case TILE_16x8_2G: return launch_sp<16, 8, TIN, TOUT, CT>(c, s, st);
+    case TILE_32x8_2G: return launch_sp<32, 8, TIN, TOUT, CT>(c, s, st);
+    case TILE_16x4_2G: return launch_sp<16, 4, TIN, TOUT, CT>(c, s, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int BX, int BY, typename TIN, typename TOUT, typename CT>
+int resident_sp()
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, reinterpret_cast<const void *>(&split_stage_kernel<BX, BY, TIN, TOUT, CT, false>),
+            2 * BX * BY, 0) != hipSuccess)
+        return 0;
+    return cus * (per > 0 ? per : 1);
+}
+
+}  // namespace
+
+bool split_tile(int tile) { return tile == TILE_16x8_2G || tile == TILE_32x8_2G || tile == TILE_16x4_2G; }
+
+int split_resident_blocks(ns_precision prec, int tile)
+{
+    const bool d = prec == NS_FP64;
+    switch (tile) {
+    case TILE_16x8_2G: return d ? resident_sp<16, 8, double, double, double>() : resident_sp<16, 8, float, float, float>();
+    case TILE_32x8_2G: return d ? resident_sp<32, 8, double, double, double>() : resident_sp<32, 8, float, float, float>();
+    case TILE_16x4_2G: return d ? resident_sp<16, 4, double, double, double>() : resident_sp<16, 4, float, float, float>();
+    default: return 0;
+    }
+}
+
+hipError_t launch_split_stage(const Consts &c, const StageArgs &s, ns_precision prec, int tile,
+                              hipStream_t st)
+{
+    if (prec == NS_FP64) return launch_sp_tile<double, double, double>(tile, c, s, st);
+    // FP32 storage: stage 1 reads the double state, stage 3 writes it.
+    if (s.mode == 1) return launch_sp_tile<double, float, float>(tile, c, s, st);
+    if (s.mode == 2) return launch_sp_tile<float, float, float>(tile, c, s, st);
+    return launch_sp_tile<float, double, float>(tile, c, s, st);
+}
+
+}  // namespace ns

@@ -133,7 +133,7 @@ def test_residual_rejects_overlap_and_small_work():
 
 def test_fused_config_validation():
     with pytest.raises(ns.NativeError):
-        ns.ns_set_fused_config(9, 0)
+        ns.ns_set_fused_config(len(ns.TILES), 0)
     with pytest.raises(ns.NativeError):
         ns.ns_set_fused_config(0, -1)
     p = ns.make_params(64)

@@ -37,7 +37,8 @@ def oracle_run(n, re, mach, dt, steps):
 # (grid, Re, M, dt, steps, tile)
 SPECS = [((16, 16, 16), 1600.0, 0.1, 3.385e-3, 4, -1),
          ((24, 20, 18), 800.0, 0.3, 2e-3, 3, 4),
-         ((37, 21, 13), 2000.0, 0.05, 1e-3, 5, 2)]
+         ((37, 21, 13), 2000.0, 0.05, 1e-3, 5, 2),
+         ((20, 28, 17), 1200.0, 0.2, 1.5e-3, 2, 10)]
 
 
 @pytest.mark.parametrize("nstreams", [1, 4])
@@ -55,7 +56,7 @@ def test_members_match_oracle_fp64(ns, nstreams):
         e = rel(got, oracle_run(n, re, m, dt, st))
         print(f"  member {n}: rel={max(e):.2e}", flush=True)
         assert max(e) < TOL, e
-    assert b.info() == (8, 3, nstreams)
+    assert b.info() == (8, len(SPECS), nstreams)
     b.close()
 
 

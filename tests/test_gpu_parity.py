@@ -235,18 +235,25 @@ def test_diagnostics_standalone(ns):
         assert abs(d[k] - want[k]) <= 1e-12 * scale + 1e-13, (k, d[k], want[k])
 
 
-@pytest.mark.parametrize("algo,prec", [("fused", "fp64"), ("stored", "fp64"), ("some", "fp64"),
-                                       ("fused", "fp32")])
-def test_per_step_diagnostics(ns, algo, prec):
+@pytest.mark.parametrize("algo,prec,tile", [("fused", "fp64", -1), ("stored", "fp64", -1),
+                                            ("some", "fp64", -1), ("fused", "fp32", -1),
+                                            ("fused", "fp64", 4), ("fused", "fp64", 8),
+                                            ("fused", "fp32", 9)])
+def test_per_step_diagnostics(ns, algo, prec, tile):
     """rk3_step's per-step records equal the oracle diagnostics of the state
-    at the start of each step."""
+    at the start of each step (default launch shape, and the one-thread and
+    two-group fused kernels explicitly)."""
     n = (32, 32, 32)
     steps, dt = 4, 3.385e-3
     ph = phys(n)
     p = params(ns, n)
     Q0 = oracle.tgv_init(ph)
     diag = torch.zeros((steps, 8), dtype=torch.float64, device="cuda")
-    gpu_rk3(ns, p, ns.ALGOS[algo], ns.PRECS[prec], Q0, dt, steps, diag=diag)
+    try:
+        ns.ns_set_fused_config(tile, 0)
+        gpu_rk3(ns, p, ns.ALGOS[algo], ns.PRECS[prec], Q0, dt, steps, diag=diag)
+    finally:
+        ns.ns_set_fused_config(-1, 0)
     rec = diag.cpu().numpy()
     Q = Q0
     # FP32 storage: kinetic energy and enstrophy come from float primitives
