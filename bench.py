@@ -113,6 +113,28 @@ class Run:
         torch.cuda.empty_cache()
 
 
+def copy_bandwidth_gbps(nbytes=1 << 31, reps=5):
+    """Device-to-device copy bandwidth (read + write bytes per second) of
+    a plain torch copy of nbytes: what a simple streaming kernel reaches on
+    this device, beside the 8 TB/s data-sheet peak."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / best / 1e9
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -377,8 +399,11 @@ def main():
             if (t.get("n") == n and t.get("precision") == args.precision
                     and t.get("source_sha256") == fused_source_hash()):
                 traffic = t.get("bytes_per_launch")
+        copy_gbps = copy_bandwidth_gbps()
+        log(f"bench: device copy {copy_gbps:.0f} GB/s; stage kernel {achieved:.0f} GB/s algorithmic")
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "copy_gbps": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4),
                     "bytes_per_launch_algorithmic": per_launch_bytes,
                     "avg_launch_us": round(avg_launch_s * 1e6, 2)}
 
