@@ -124,14 +124,52 @@ fused_stage_kernel(Consts c, StageArgs s)
     constexpr int NR = DIAG ? 6 : 5;    // ring entries: residuals (+ omega_z)
     const int64_t col = (int64_t)gy * c.nx + gx;   // own (x, y) offset in a plane
 
-    // Plane offsets of the points this thread loads (fixed for the march).
-    int loff[NLOAD];
+    // FP32 storage, stage 1: the input is the exact double state, which is
+    // also the RK accumulator of the output point.  Each thread then loads
+    // its own column as load slot 0 (the halo ring goes to the other slots)
+    // and keeps that point's doubles for the three steps until the point is
+    // finished, instead of reading them from memory a second time.
+    constexpr bool OWN = DEV && std::is_same<TIN, double>::value;
+
+    // Plane offsets and LDS cells of the points this thread loads (fixed
+    // for the march); lcell < 0 marks an unused slot.
+    int loff[NLOAD], lcell[NLOAD];
 #pragma unroll
     for (int r = 0; r < NLOAD; ++r) {
-        const int idx = tid + r * NT;
+        int lx = 0, ly = 0;
+        lcell[r] = -1;
+        if constexpr (OWN) {
+            if (r == 0) {
+                lx = tx + 2;
+                ly = ty + 2;
+                lcell[r] = ly * HX + lx;
+            } else {
+                // k-th point of the radius-2 ring around the tile: two rows
+                // on top, two at the bottom, then two columns on each side
+                const int k = tid + (r - 1) * NT;
+                if (k < HP - NT) {
+                    if (k < 4 * HX) {
+                        const int row = k / HX;
+                        lx = k % HX;
+                        ly = row < 2 ? row : HY - 4 + row;
+                    } else {
+                        const int q = k - 4 * HX, cc = q % 4;
+                        ly = 2 + q / 4;
+                        lx = cc < 2 ? cc : HX - 4 + cc;
+                    }
+                    lcell[r] = ly * HX + lx;
+                }
+            }
+        } else {
+            const int idx = tid + r * NT;
+            if (idx < HP) {
+                lx = idx % HX;
+                ly = idx / HX;
+                lcell[r] = idx;
+            }
+        }
         loff[r] = 0;
-        if (idx < HP) {
-            const int lx = idx % HX, ly = idx / HX;
+        if (lcell[r] >= 0) {
             int xx = (x0 + lx - 2) % c.nx;
             if (xx < 0) xx += c.nx;
             int yy = (y0 + ly - 2) % c.ny;
@@ -153,6 +191,11 @@ fused_stage_kernel(Consts c, StageArgs s)
     CT ra[5][NR];                 // ring: pending residuals (5) (+ omega_z)
     TIN pf[NLOAD][5];             // next plane, prefetched
     double accpf[5];              // accumulator (or exact state) of the output point
+    double ocol[OWN ? 3 : 1][5];  // exact state of the own column, three planes (OWN)
+#pragma unroll
+    for (int q = 0; q < (OWN ? 3 : 1); ++q)
+#pragma unroll
+        for (int f = 0; f < 5; ++f) ocol[q][f] = 0.0;
     double dsum[DIAG ? 7 : 1];
 #pragma unroll
     for (int k = 0; k < (DIAG ? 7 : 1); ++k) dsum[k] = 0.0;
@@ -184,8 +227,8 @@ fused_stage_kernel(Consts c, StageArgs s)
     auto stage_plane = [&](int b) {
 #pragma unroll
         for (int r = 0; r < NLOAD; ++r) {
-            const int idx = tid + r * NT;
-            if (idx < HP) {
+            const int idx = lcell[r];
+            if (idx >= 0) {
                 const CT rho = to_ct<TIN, CT>(pf[r][0], c.rho_ref);
                 const CT m0 = to_ct<TIN, CT>(pf[r][1], 0.0);
                 const CT m1 = to_ct<TIN, CT>(pf[r][2], 0.0);
@@ -212,6 +255,16 @@ fused_stage_kernel(Consts c, StageArgs s)
         }
     };
 
+    // own-column ring: planes zp+1, zp, zp-1 after the shift at the end of step zp
+    auto shift_ocol = [&]() {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            ocol[2][f] = ocol[1][f];
+            ocol[1][f] = ocol[0][f];
+            ocol[0][f] = (double)pf[0][f];
+        }
+    };
+
     // One plane of the march.  PH = (zp - z0 + 2) mod 5 selects ring slots:
     // plane zp + k lives in slot (PH + k) mod 5.
     auto step = [&](auto phc, int zp) {
@@ -231,11 +284,18 @@ fused_stage_kernel(Consts c, StageArgs s)
             // stages 2 and 3 read the accumulator; the residual and stage 1
             // read the exact double input state (unused for the residual).
             // Threads with no output point read a valid address they ignore.
-            const double *src = (s.mode >= 2) ? s.acc_in : (const double *)s.qin;
-            const int zc = fin ? zf : z0;
-            const int64_t pidx = (int64_t)zc * c.nxy + (active ? col : 0);
+            if constexpr (OWN) {
+                // stage 1 only: the exact state of plane zp - 2, loaded
+                // three steps ago as this thread's slot 0
 #pragma unroll
-            for (int f = 0; f < 5; ++f) accpf[f] = __builtin_nontemporal_load(src + f * N + pidx);
+                for (int f = 0; f < 5; ++f) accpf[f] = ocol[2][f];
+            } else {
+                const double *src = (s.mode >= 2) ? s.acc_in : (const double *)s.qin;
+                const int zc = fin ? zf : z0;
+                const int64_t pidx = (int64_t)zc * c.nxy + (active ? col : 0);
+#pragma unroll
+                for (int f = 0; f < 5; ++f) accpf[f] = __builtin_nontemporal_load(src + f * N + pidx);
+            }
         }
         load_plane(zp + 1);
 
@@ -484,12 +544,14 @@ fused_stage_kernel(Consts c, StageArgs s)
             }
         }
 
+        if constexpr (OWN) shift_ocol();
         lds_barrier();
     };
 
     // prologue: plane z0 - 2 into LDS buffer 0
     load_plane(z0 - 2);
     stage_plane(0);
+    if constexpr (OWN) shift_ocol();
     lds_barrier();
 
     // The march covers planes z0-2 .. z1+1, padded to a multiple of 5;
