@@ -162,9 +162,10 @@ ns_status diagnostics(const ns_params *p, const double *state,
  * energy equation and the viscous terms); zchunk is the number of
  * z planes one block marches through (>= 1; 0 = automatic: the length that
  * minimises (rounds of device-resident blocks) x (planes each block
- * marches, chunk + 4 halo planes)).  tile = -1 restores the automatic
- * choice.  For a given tile, residuals and states
- * are bitwise independent of zchunk; different tiles are separate compiled
+ * marches, chunk + 4 halo planes; + 5 for tiles 8-10)).  tile = -1
+ * restores the automatic choice: tile 9 for NS_FP64, tile 0 for
+ * NS_FP32_STORE.  For a given tile, residuals and states are bitwise
+ * independent of zchunk (tiles 8-10 also of the tile among them); different tiles are separate compiled
  * instances and may differ at the rounding level (the compiler can contract
  * a multiply-add differently); per-step diagnostics also differ in the
  * order of their sums.
