@@ -81,10 +81,14 @@ using SIC = std::integral_constant<int, V>;
 
 }  // namespace
 
-template <int BX, int BY, typename TIN, typename TOUT, typename CT, bool DIAG>
+// OWN (stage 1 only): the input state is also the RK accumulator of the
+// output point; group M then takes the accumulator of its four fields from
+// its own column's plane loads instead of reading the state again.
+template <int BX, int BY, typename TIN, typename TOUT, typename CT, bool DIAG, bool OWN>
 __global__ void __launch_bounds__(2 * BX * BY)
 split_stage_kernel(Consts c, StageArgs s)
 {
+    static_assert(!OWN || std::is_same<TIN, double>::value, "OWN needs the double state as input");
     constexpr bool DEV = std::is_same<CT, float>::value;
     constexpr int HX = BX + 4, HY = BY + 4, HP = HX * HY, NT = BX * BY;
     constexpr int NLOAD = (HP + NT - 1) / NT;
@@ -165,6 +169,13 @@ split_stage_kernel(Consts c, StageArgs s)
         CT rp[4];          // plane zp - 2 with its z terms, V still missing
         TIN pf[NLOAD][5];  // next plane, prefetched
         double acc[4];
+        double ocol[OWN ? 3 : 1][4];   // own column's exact state, three planes (OWN)
+#pragma unroll
+        for (int q = 0; q < (OWN ? 3 : 1); ++q)
+#pragma unroll
+            for (int f = 0; f < 4; ++f) ocol[q][f] = 0.0;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) acc[f] = 0.0;
 #pragma unroll
         for (int q = 0; q < 5; ++q)
 #pragma unroll
@@ -172,13 +183,46 @@ split_stage_kernel(Consts c, StageArgs s)
 #pragma unroll
         for (int f = 0; f < 4; ++f) rp[f] = CT(0);
 
-        int loff[NLOAD];
+        // Plane offsets and LDS cells of the points this thread loads;
+        // lcell < 0 marks an unused slot.  With OWN, slot 0 is the thread's
+        // own column and the radius-2 ring around the tile goes to the
+        // other slots (two rows on top, two at the bottom, then two
+        // columns on each side).
+        int loff[NLOAD], lcell[NLOAD];
 #pragma unroll
         for (int r = 0; r < NLOAD; ++r) {
-            const int idx = pt + r * NT;
+            int lx = 0, ly = 0;
+            lcell[r] = -1;
+            if constexpr (OWN) {
+                if (r == 0) {
+                    lx = tx + 2;
+                    ly = ty + 2;
+                    lcell[r] = ly * HX + lx;
+                } else {
+                    const int k = pt + (r - 1) * NT;
+                    if (k < HP - NT) {
+                        if (k < 4 * HX) {
+                            const int row = k / HX;
+                            lx = k % HX;
+                            ly = row < 2 ? row : HY - 4 + row;
+                        } else {
+                            const int q = k - 4 * HX, cc = q % 4;
+                            ly = 2 + q / 4;
+                            lx = cc < 2 ? cc : HX - 4 + cc;
+                        }
+                        lcell[r] = ly * HX + lx;
+                    }
+                }
+            } else {
+                const int idx = pt + r * NT;
+                if (idx < HP) {
+                    lx = idx % HX;
+                    ly = idx / HX;
+                    lcell[r] = idx;
+                }
+            }
             loff[r] = 0;
-            if (idx < HP) {
-                const int lx = idx % HX, ly = idx / HX;
+            if (lcell[r] >= 0) {
                 int xx = (x0 + lx - 2) % c.nx;
                 if (xx < 0) xx += c.nx;
                 int yy = (y0 + ly - 2) % c.ny;
@@ -200,8 +244,8 @@ split_stage_kernel(Consts c, StageArgs s)
         auto stage_plane = [&](int b) {
 #pragma unroll
             for (int r = 0; r < NLOAD; ++r) {
-                const int idx = pt + r * NT;
-                if (idx < HP) {
+                const int idx = lcell[r];
+                if (idx >= 0) {
                     const CT rho = sp_to_ct<TIN, CT>(pf[r][0], c.rho_ref);
                     const CT m0 = sp_to_ct<TIN, CT>(pf[r][1], 0.0);
                     const CT m1 = sp_to_ct<TIN, CT>(pf[r][2], 0.0);
@@ -226,6 +270,18 @@ split_stage_kernel(Consts c, StageArgs s)
             }
         };
 
+        // OWN: at the end of step zp, acc takes plane zp - 2 (finished in
+        // step zp + 1) and the ring moves on to planes zp + 1, zp, zp - 1
+        auto shift_ocol = [&]() {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                acc[f] = ocol[2][f];
+                ocol[2][f] = ocol[1][f];
+                ocol[1][f] = ocol[0][f];
+                ocol[0][f] = (double)pf[0][f];
+            }
+        };
+
         auto step = [&](auto phc, int zp) {
             constexpr int PH = decltype(phc)::value;
             constexpr int SM2 = (PH + 3) % 5, SM1 = (PH + 4) % 5, S0 = PH;
@@ -234,7 +290,7 @@ split_stage_kernel(Consts c, StageArgs s)
             const int b = (zp - z0) & 1;
             const int zf = zp - 3;
             const bool fin = active && zf >= z0 && zf < z1;
-            {
+            if constexpr (!OWN) {
                 // accumulator (stages 2, 3) or exact input state of the
                 // point finished in this step; idle threads read a valid
                 // address they ignore
@@ -344,12 +400,14 @@ split_stage_kernel(Consts c, StageArgs s)
 #undef RHOF
 #undef DZ1
             }
+            if constexpr (OWN) shift_ocol();
             lds_barrier();
         };
 
         // prologue: plane z0 - 2 into LDS buffer 0
         load_plane(z0 - 2);
         stage_plane(0);
+        if constexpr (OWN) shift_ocol();
         lds_barrier();
         for (int it = 0; it < L; it += 5) {
             const int zp = z0 - 2 + it;
@@ -549,13 +607,19 @@ hipError_t launch_sp(const Consts &c, const StageArgs &s, hipStream_t st)
 {
     dim3 block(2 * BX * BY, 1, 1);
     dim3 grid((c.nx + BX - 1) / BX, (c.ny + BY - 1) / BY, (c.nz + s.zchunk - 1) / s.zchunk);
+    // stage 1 reads the double state, which is also its accumulator
     if constexpr (std::is_same<TIN, double>::value) {
-        if (s.diag_partial != nullptr && s.mode == 1) {
-            hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, true>), grid, block, 0, st, c, s);
+        if (s.mode == 1) {
+            if (s.diag_partial != nullptr)
+                hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, true, true>), grid, block, 0,
+                                   st, c, s);
+            else
+                hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, false, true>), grid, block, 0,
+                                   st, c, s);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, false>), grid, block, 0, st, c, s);
+    hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, false, false>), grid, block, 0, st, c, s);
     return hipGetLastError();
 }
 
@@ -577,7 +641,7 @@ int resident_sp()
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per, reinterpret_cast<const void *>(&split_stage_kernel<BX, BY, TIN, TOUT, CT, false>),
+            &per, reinterpret_cast<const void *>(&split_stage_kernel<BX, BY, TIN, TOUT, CT, false, false>),
             2 * BX * BY, 0) != hipSuccess)
         return 0;
     return cus * (per > 0 ? per : 1);
