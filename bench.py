@@ -227,8 +227,8 @@ def batched(tuner, seed=0, count=64, steps=200):
     out = {"instances": count, "seed": seed, "steps": steps, "updates": upd,
            "total_points": sum(i["n"] ** 3 for i in insts)}
     stream = torch.cuda.current_stream()
-    for prec in ("fp32", "fp64"):
-        b = ns.Batch(count, prec, nstreams=3)
+    for prec, graphs in (("fp32", False), ("fp64", False), ("fp32", True)):
+        b = ns.Batch(count, prec, nstreams=3, graphs=graphs)
         for i in insts:
             tile, zc = tuner.lookup(i["n"], prec)
             b.add(i["n"], reynolds=i["reynolds"], mach=i["mach"], dt=i["dt"], steps=i["steps"],
@@ -244,8 +244,9 @@ def batched(tuner, seed=0, count=64, steps=200):
         wall = time.perf_counter() - t0
         ms = e0.elapsed_time(e1)
         b.close()
-        out[f"batch_{prec}"] = {"updates_per_s": upd / (ms * 1e-3), "ms": ms, "wall_s": wall}
-        log(f"bench batched {prec}: {upd / (ms * 1e-3):.3e} updates/s")
+        key = f"batch_{prec}" + ("_graphs" if graphs else "")
+        out[key] = {"updates_per_s": upd / (ms * 1e-3), "ms": ms, "wall_s": wall}
+        log(f"bench batched {key}: {upd / (ms * 1e-3):.3e} updates/s")
     runs = []
     for i in insts:
         p = ns.make_params(i["n"], reynolds=i["reynolds"], mach=i["mach"])
@@ -464,6 +465,7 @@ def main():
             batch_out = dict(per_seed[0])
             batch_out["seeds"] = {
                 str(b["seed"]): {"batch_fp32": b["batch_fp32"]["updates_per_s"],
+                                 "batch_fp32_graphs": b["batch_fp32_graphs"]["updates_per_s"],
                                  "batch_fp64": b["batch_fp64"]["updates_per_s"],
                                  "sequential_fp64": b["sequential_fp64"]["updates_per_s"],
                                  "ratio": b["batch_fp32_over_sequential_fp64"]}

@@ -256,6 +256,18 @@ ns_status ns_batch_remove(ns_batch *b, int32_t slot);
  * `stream` sees the results.  Asynchronous. */
 ns_status ns_batch_step(ns_batch *b, int32_t nsteps, void *stream);
 
+/* Run later ns_batch_step calls through HIP graphs (enable = 1) or eagerly
+ * (0, the default).  With graphs, 8 batch steps of the members that have
+ * steps left are captured once into a graph on a batch-owned stream, and
+ * the graph is replayed while that set of members stays the same; adding,
+ * removing or a member running out of steps triggers a new capture, and
+ * steps that do not fill a whole graph run eagerly.  The launches are the
+ * eager ones, so results are bit-identical.  The first enable creates a
+ * stream and two events (NS_ERR_DEVICE on failure); NS_ERR_ARG for other
+ * values of enable.  A failed capture or replay makes ns_batch_step return
+ * NS_ERR_DEVICE. */
+ns_status ns_batch_set_graphs(ns_batch *b, int32_t enable);
+
 /* Fill host arrays of max_instances entries (any may be NULL) with each
  * slot's steps left (-1 for a free slot) and steps queued so far; with
  * diag non-NULL (batch created with diagnostics, else NS_ERR_ARG) copy the

@@ -12,6 +12,6 @@ from ._native import (ALGOS, DIAG_NAMES, EXPORTS, NS_ALGO_FUSED, NS_ALGO_SOME, N
                       ns_get_fused_config, ns_get_fused_order, ns_residual, ns_set_fused_config, ns_set_fused_order, ns_state_bytes,
                       ns_workspace_bytes, rk3_step, status_string, tgv_init)
 from ._native import (ns_batch_add, ns_batch_create, ns_batch_destroy, ns_batch_info,  # noqa: F401
-                      ns_batch_poll, ns_batch_remove, ns_batch_step)
+                      ns_batch_poll, ns_batch_remove, ns_batch_set_graphs, ns_batch_step)
 from .batch import Batch  # noqa: F401
 from .solver import Solver  # noqa: F401

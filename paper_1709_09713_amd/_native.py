@@ -72,7 +72,7 @@ EXPORTS = ("ns_status_string", "ns_state_bytes", "ns_workspace_bytes",
            "ns_set_fused_config", "ns_get_fused_config", "ns_set_fused_order",
            "ns_get_fused_order",
            "ns_batch_create", "ns_batch_destroy", "ns_batch_add", "ns_batch_remove",
-           "ns_batch_step", "ns_batch_poll", "ns_batch_info")
+           "ns_batch_step", "ns_batch_set_graphs", "ns_batch_poll", "ns_batch_info")
 
 
 class NativeError(RuntimeError):
@@ -125,6 +125,7 @@ def lib():
                         ("ns_batch_add", [vp, ctypes.POINTER(ns_instance), pi32]),
                         ("ns_batch_remove", [vp, i32]),
                         ("ns_batch_step", [vp, i32, vp]),
+                        ("ns_batch_set_graphs", [vp, i32]),
                         ("ns_batch_poll", [vp, pi32, pi32, ctypes.POINTER(ns_diag), vp]),
                         ("ns_batch_info", [vp, pi32, pi32, pi32])):
             getattr(L, f).restype = ctypes.c_int
@@ -265,6 +266,10 @@ def ns_batch_remove(handle: int, slot: int):
 
 def ns_batch_step(handle: int, nsteps: int, stream=None):
     _check(lib().ns_batch_step(handle, int(nsteps), _stream(stream)), "ns_batch_step")
+
+
+def ns_batch_set_graphs(handle: int, enable: bool):
+    _check(lib().ns_batch_set_graphs(handle, 1 if enable else 0), "ns_batch_set_graphs")
 
 
 def ns_batch_info(handle: int):

@@ -13,7 +13,7 @@ from . import _native as nat
 
 class Batch:
     def __init__(self, max_instances: int, precision: str = "fp32", nstreams: int = 3,
-                 diagnostics: bool = False, device="cuda"):
+                 diagnostics: bool = False, graphs: bool = False, device="cuda"):
         self.prec = nat.PRECS[precision]
         self.precision = precision
         self.max_instances = max_instances
@@ -21,6 +21,12 @@ class Batch:
         self.device = torch.device(device)
         self.handle = nat.ns_batch_create(max_instances, self.prec, nstreams, diagnostics)
         self.members = {}   # slot -> (params, state, work)
+        if graphs:
+            self.set_graphs(True)
+
+    def set_graphs(self, enable: bool):
+        """Replay later steps through captured HIP graphs (bit-identical)."""
+        nat.ns_batch_set_graphs(self.handle, enable)
 
     @staticmethod
     def footprint(n, precision: str) -> int:

@@ -8,6 +8,15 @@
 // from and join back into the caller's stream, so the batch is ordered like
 // any other stream work.  The launches are exactly rk3_step's, so a
 // member's result does not depend on which other members share the batch.
+//
+// Optionally (ns_batch_set_graphs) kGraphSteps batch steps -- every
+// stepping member's stage launches on their streams, forked from and joined
+// into a batch-owned origin stream -- are captured once into a HIP graph
+// and replayed while the set of stepping members stays the same (steps
+// that do not fill a whole graph run eagerly); the graph is captured again
+// when a member is added, removed or runs out of steps.  Every kernel
+// argument is the same from step to step, so a replay is exactly the eager
+// steps.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -20,6 +29,7 @@
 namespace ns {
 
 constexpr int kMaxStreams = 8;
+constexpr int32_t kGraphSteps = 8;   // steps per captured graph
 constexpr int kMaxInstances = 4096;
 
 struct Member {
@@ -43,10 +53,28 @@ struct Batch {
     hipEvent_t join[kMaxStreams] = {};
     int64_t load[kMaxStreams] = {};
     std::vector<Member> m;
+    // graph replay
+    bool graphs = false;
+    hipStream_t origin = nullptr;       // capture and replay stream
+    hipEvent_t gin = nullptr, gout = nullptr;
+    hipGraphExec_t gexec = nullptr;     // one step of the current stepping set
 };
+
+static void drop_graph(Batch *b)
+{
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+}
 
 static void destroy(Batch *b)
 {
+    if (b->origin) (void)hipStreamSynchronize(b->origin);
+    drop_graph(b);
+    if (b->origin) (void)hipStreamDestroy(b->origin);
+    if (b->gin) (void)hipEventDestroy(b->gin);
+    if (b->gout) (void)hipEventDestroy(b->gout);
     for (int i = 0; i < kMaxStreams; ++i) {
         if (b->streams[i]) {
             (void)hipStreamSynchronize(b->streams[i]);
@@ -61,6 +89,58 @@ static void destroy(Batch *b)
 static bool overlaps(const char *a0, const char *a1, const char *b0, const char *b1)
 {
     return a0 < b1 && b0 < a1;
+}
+
+// Slots with steps left, largest grids first (stable), so that small grids,
+// which cannot fill the device alone, run beside large ones on the other
+// streams.
+static std::vector<int> stepping_order(const Batch *b)
+{
+    std::vector<int> order;
+    for (int i = 0; i < b->max_inst; ++i)
+        if (b->m[i].used && b->m[i].steps_left > 0) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return b->m[x].points > b->m[y].points; });
+    return order;
+}
+
+// Queue nsteps steps of the members in `order`, forked once from `s` and
+// joined once back into it.  Step-major: every member's step r is queued
+// before step r + 1, so each internal stream is fed as the host walks the
+// list and runs ahead of the others as far as its own work allows.
+static hipError_t enqueue_steps(Batch *b, const std::vector<int> &order, int32_t nsteps, hipStream_t s)
+{
+    hipError_t e = hipEventRecord(b->fork, s);
+    for (int k = 0; e == hipSuccess && k < b->nstreams; ++k) e = hipStreamWaitEvent(b->streams[k], b->fork, 0);
+    for (int32_t r = 0; r < nsteps; ++r) {
+        for (size_t j = 0; e == hipSuccess && j < order.size(); ++j) {
+            const int i = order[j];
+            const Member &m = b->m[i];
+            ns_diag *d = b->diag ? b->d_diag + i : nullptr;
+            e = enqueue_fused_step(m.plan, m.dt, d, b->streams[m.stream]);
+        }
+    }
+    for (int k = 0; e == hipSuccess && k < b->nstreams; ++k) {
+        e = hipEventRecord(b->join[k], b->streams[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join[k], 0);
+    }
+    return e;
+}
+
+// Capture kGraphSteps steps of `order` on the origin stream into b->gexec.
+static hipError_t capture_steps(Batch *b, const std::vector<int> &order)
+{
+    drop_graph(b);
+    hipError_t e = hipStreamBeginCapture(b->origin, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return e;
+    const hipError_t eq = enqueue_steps(b, order, kGraphSteps, b->origin);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->origin, &g);
+    if (eq != hipSuccess) e = eq;
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) b->gexec = nullptr;
+    return e;
 }
 
 }  // namespace ns
@@ -157,6 +237,7 @@ ns_status ns_batch_add(ns_batch *b, const ns_instance *inst, int32_t *slot)
     m.work_hi = w1;
     b->load[best] += m.points;
     *slot = free_slot;
+    drop_graph(b);
     return NS_OK;
 }
 
@@ -166,6 +247,7 @@ ns_status ns_batch_remove(ns_batch *b, int32_t slot)
     Member &m = b->m[slot];
     b->load[m.stream] -= m.points;
     m = Member();
+    drop_graph(b);
     return NS_OK;
 }
 
@@ -173,35 +255,50 @@ ns_status ns_batch_step(ns_batch *b, int32_t nsteps, void *stream)
 {
     if (!b || nsteps < 0) return NS_ERR_ARG;
     hipStream_t caller = (hipStream_t)stream;
-    bool any = false;
-    for (const Member &m : b->m) any = any || (m.used && m.steps_left > 0);
-    if (!any || nsteps == 0) return NS_OK;
-    NS_HIP_OK(hipEventRecord(b->fork, caller));
-    for (int s = 0; s < b->nstreams; ++s) NS_HIP_OK(hipStreamWaitEvent(b->streams[s], b->fork, 0));
-    // Largest members first within a step, so that small grids (which
-    // cannot fill the device alone) run beside large ones on the other
-    // streams.
-    std::vector<int> order;
-    for (int i = 0; i < b->max_inst; ++i)
-        if (b->m[i].used) order.push_back(i);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return b->m[x].points > b->m[y].points; });
-    // Step-major order: every member's step k is queued before any step
-    // k + 1, so each internal stream is fed as the host walks the list.
-    for (int32_t k = 0; k < nsteps; ++k) {
+    while (nsteps > 0) {
+        const std::vector<int> order = stepping_order(b);
+        if (order.empty()) break;
+        // steps for which the stepping set stays the same
+        int32_t k = nsteps;
+        for (int i : order) k = std::min(k, (int32_t)b->m[i].steps_left);
+        int32_t eager = k;
+        if (b->graphs && k >= kGraphSteps) {
+            // whole graphs of kGraphSteps steps on the origin stream, ordered
+            // between the caller's earlier and later work
+            if (!b->gexec) NS_HIP_OK(capture_steps(b, order));
+            NS_HIP_OK(hipEventRecord(b->gin, caller));
+            NS_HIP_OK(hipStreamWaitEvent(b->origin, b->gin, 0));
+            for (int32_t r = 0; r + kGraphSteps <= k; r += kGraphSteps)
+                NS_HIP_OK(hipGraphLaunch(b->gexec, b->origin));
+            NS_HIP_OK(hipEventRecord(b->gout, b->origin));
+            NS_HIP_OK(hipStreamWaitEvent(caller, b->gout, 0));
+            eager = k % kGraphSteps;
+        }
+        if (eager > 0) NS_HIP_OK(enqueue_steps(b, order, eager, caller));
+        bool finished = false;
         for (int i : order) {
             Member &m = b->m[i];
-            if (m.steps_left <= 0) continue;
-            ns_diag *d = b->diag ? b->d_diag + i : nullptr;
-            NS_HIP_OK(enqueue_fused_step(m.plan, m.dt, d, b->streams[m.stream]));
-            --m.steps_left;
-            ++m.steps_done;
+            m.steps_left -= k;
+            m.steps_done += k;
+            finished = finished || m.steps_left == 0;
         }
+        if (finished) drop_graph(b);   // the stepping set changes
+        nsteps -= k;
     }
-    for (int s = 0; s < b->nstreams; ++s) {
-        NS_HIP_OK(hipEventRecord(b->join[s], b->streams[s]));
-        NS_HIP_OK(hipStreamWaitEvent(caller, b->join[s], 0));
+    return NS_OK;
+}
+
+ns_status ns_batch_set_graphs(ns_batch *b, int32_t enable)
+{
+    if (!b || (enable != 0 && enable != 1)) return NS_ERR_ARG;
+    if (enable && !b->origin) {
+        if (hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->gin, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&b->gout, hipEventDisableTiming) != hipSuccess)
+            return NS_ERR_DEVICE;
     }
+    if (!enable) drop_graph(b);
+    b->graphs = enable != 0;
     return NS_OK;
 }
 

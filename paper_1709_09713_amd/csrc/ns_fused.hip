@@ -191,9 +191,9 @@ fused_stage_kernel(Consts c, StageArgs s)
     CT ra[5][NR];                 // ring: pending residuals (5) (+ omega_z)
     TIN pf[NLOAD][5];             // next plane, prefetched
     double accpf[5];              // accumulator (or exact state) of the output point
-    double ocol[OWN ? 3 : 1][5];  // exact state of the own column, three planes (OWN)
+    double ocol[3][5];            // exact state of the own column, three planes (OWN only)
 #pragma unroll
-    for (int q = 0; q < (OWN ? 3 : 1); ++q)
+    for (int q = 0; q < 3; ++q)
 #pragma unroll
         for (int f = 0; f < 5; ++f) ocol[q][f] = 0.0;
     double dsum[DIAG ? 7 : 1];

@@ -169,9 +169,9 @@ split_stage_kernel(Consts c, StageArgs s)
         CT rp[4];          // plane zp - 2 with its z terms, V still missing
         TIN pf[NLOAD][5];  // next plane, prefetched
         double acc[4];
-        double ocol[OWN ? 3 : 1][4];   // own column's exact state, three planes (OWN)
+        double ocol[3][4];             // own column's exact state, three planes (OWN only)
 #pragma unroll
-        for (int q = 0; q < (OWN ? 3 : 1); ++q)
+        for (int q = 0; q < 3; ++q)
 #pragma unroll
             for (int f = 0; f < 4; ++f) ocol[q][f] = 0.0;
 #pragma unroll

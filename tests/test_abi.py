@@ -171,6 +171,7 @@ def test_batch_calls_reject_null_handle():
     import ctypes
     L = ns.lib()
     assert L.ns_batch_step(None, 1, None) == ns.NS_ERR_ARG
+    assert L.ns_batch_set_graphs(None, 1) == ns.NS_ERR_ARG
     assert L.ns_batch_remove(None, 0) == ns.NS_ERR_ARG
     assert L.ns_batch_destroy(None) == ns.NS_ERR_ARG
     assert L.ns_batch_poll(None, None, None, None, None) == ns.NS_ERR_ARG

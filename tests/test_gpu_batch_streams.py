@@ -170,3 +170,39 @@ def test_rejects_bad_members(ns):
         ns.ns_batch_add(b2.handle, p, 1e-3, 1, state, work, tile=11)
     assert e.value.status == ns.NS_ERR_ARG
     b2.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replays_match_eager(ns, prec):
+    """Steps replayed from captured graphs equal the eager steps bit for bit
+    after every replay, with the program's own eager work between replays;
+    a member running out of steps forces a new capture."""
+    print(f"batch graphs vs eager {prec}", flush=True)
+    specs = [((16, 16, 16), 1600.0, 0.1, 3.385e-3, 40),
+             ((24, 20, 18), 800.0, 0.3, 2e-3, 40),
+             ((20, 28, 17), 1200.0, 0.2, 1.5e-3, 28)]
+    eager = ns.Batch(4, prec, nstreams=2, diagnostics=True)
+    graph = ns.Batch(4, prec, nstreams=2, diagnostics=True, graphs=True)
+    se = [eager.add(n, reynolds=re, mach=m, dt=dt, steps=st) for n, re, m, dt, st in specs]
+    sg = [graph.add(n, reynolds=re, mach=m, dt=dt, steps=st) for n, re, m, dt, st in specs]
+    for chunk in range(5):          # one graph of 8 steps per call
+        eager.step(8)
+        graph.step(8)
+        torch.cuda.synchronize()
+        busy = torch.ones(1 << 20, dtype=torch.float64, device="cuda").mul_(2.0).sum()
+        assert float(busy) == 2.0 * (1 << 20)
+        for a, b in zip(se, sg):
+            assert torch.equal(eager.members[a][1], graph.members[b][1]), (chunk, a)
+        le, de, diag_e = eager.poll()
+        lg, dg, diag_g = graph.poll()
+        assert le == lg and de == dg
+        for a, b in zip(se, sg):
+            assert diag_e[a] == diag_g[b], (chunk, a)
+    left, done, _ = graph.poll()
+    assert [done[s] for s in sg] == [st for *_, st in specs]
+    if prec == "fp64":
+        for s, (n, re, m, dt, st) in zip(sg, specs):
+            e = rel(graph.members[s][1].cpu().numpy(), oracle_run(n, re, m, dt, st))
+            assert max(e) < TOL, e
+    eager.close()
+    graph.close()
