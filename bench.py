@@ -352,7 +352,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
                           "(multi-GPU slab decomposition is a design, not an implementation)"}))
         sys.exit(2)
     if not torch.cuda.is_available():
