@@ -84,14 +84,20 @@ using SIC = std::integral_constant<int, V>;
 // OWN (stage 1 only): the input state is also the RK accumulator of the
 // output point; group M then takes the accumulator of its four fields from
 // its own column's plane loads instead of reading the state again.
-template <int BX, int BY, typename TIN, typename TOUT, typename CT, bool DIAG, bool OWN>
+// PAIR (even nx, not with OWN): group M loads the halo plane two x-neighbours
+// per lane with one 2-wide load, halving its plane-load instructions; pairs
+// start at even x, so with nx even they never straddle the periodic wrap.
+template <int BX, int BY, typename TIN, typename TOUT, typename CT, bool DIAG, bool OWN, bool PAIR>
 __global__ void __launch_bounds__(2 * BX * BY)
 split_stage_kernel(Consts c, StageArgs s)
 {
     static_assert(!OWN || std::is_same<TIN, double>::value, "OWN needs the double state as input");
+    static_assert(!(OWN && PAIR), "OWN loads single points");
+    static_assert(BX % 2 == 0, "pairs need an even tile width");
     constexpr bool DEV = std::is_same<CT, float>::value;
     constexpr int HX = BX + 4, HY = BY + 4, HP = HX * HY, NT = BX * BY;
-    constexpr int NLOAD = (HP + NT - 1) / NT;
+    constexpr int PW = PAIR ? 2 : 1;                        // points per load slot
+    constexpr int NLOAD = (HP + PW * NT - 1) / (PW * NT);
     constexpr int NW = 2 * NT / 64;
     static_assert(NT % 64 == 0, "each group must be whole waves");
     enum { L_RHO, L_M0, L_M1, L_M2, L_E, L_U, L_V, L_W, L_P, L_T, NF };
@@ -167,7 +173,7 @@ split_stage_kernel(Consts c, StageArgs s)
         CT qz[5][NZ];      // ring: rho, u, v, w of the own column
         CT ra[5][4];       // ring: pending mass and momentum residuals
         CT rp[4];          // plane zp - 2 with its z terms, V still missing
-        TIN pf[NLOAD][5];  // next plane, prefetched
+        TIN pf[NLOAD][5][PW];  // next plane, prefetched
         double acc[4];
         double ocol[3][4];             // own column's exact state, three planes (OWN only)
 #pragma unroll
@@ -213,6 +219,13 @@ split_stage_kernel(Consts c, StageArgs s)
                         lcell[r] = ly * HX + lx;
                     }
                 }
+            } else if constexpr (PAIR) {
+                const int q = pt + r * NT;          // pair index
+                if (q < HP / 2) {
+                    lx = 2 * (q % (HX / 2));
+                    ly = q / (HX / 2);
+                    lcell[r] = ly * HX + lx;
+                }
             } else {
                 const int idx = pt + r * NT;
                 if (idx < HP) {
@@ -238,19 +251,30 @@ split_stage_kernel(Consts c, StageArgs s)
             for (int r = 0; r < NLOAD; ++r) {
                 const int64_t g = base + loff[r];
 #pragma unroll
-                for (int f = 0; f < 5; ++f) pf[r][f] = qin[g + f * N];
+                for (int f = 0; f < 5; ++f) {
+                    if constexpr (PAIR) {
+                        typedef TIN pair_t __attribute__((ext_vector_type(2)));
+                        const pair_t v = *(const pair_t *)(qin + g + f * N);
+                        pf[r][f][0] = v.x;
+                        pf[r][f][1] = v.y;
+                    } else {
+                        pf[r][f][0] = qin[g + f * N];
+                    }
+                }
             }
         };
         auto stage_plane = [&](int b) {
 #pragma unroll
-            for (int r = 0; r < NLOAD; ++r) {
-                const int idx = lcell[r];
-                if (idx >= 0) {
-                    const CT rho = sp_to_ct<TIN, CT>(pf[r][0], c.rho_ref);
-                    const CT m0 = sp_to_ct<TIN, CT>(pf[r][1], 0.0);
-                    const CT m1 = sp_to_ct<TIN, CT>(pf[r][2], 0.0);
-                    const CT m2 = sp_to_ct<TIN, CT>(pf[r][3], 0.0);
-                    const CT E = sp_to_ct<TIN, CT>(pf[r][4], c.rhoE_ref);
+            for (int r = 0; r < NLOAD; ++r)
+#pragma unroll
+            for (int j = 0; j < PW; ++j) {
+                const int idx = lcell[r] + j;
+                if (lcell[r] >= 0) {
+                    const CT rho = sp_to_ct<TIN, CT>(pf[r][0][j], c.rho_ref);
+                    const CT m0 = sp_to_ct<TIN, CT>(pf[r][1][j], 0.0);
+                    const CT m1 = sp_to_ct<TIN, CT>(pf[r][2][j], 0.0);
+                    const CT m2 = sp_to_ct<TIN, CT>(pf[r][3][j], 0.0);
+                    const CT E = sp_to_ct<TIN, CT>(pf[r][4][j], c.rhoE_ref);
                     const CT rhof = DEV ? CT(1) + rho : rho;
                     const CT inv = sp_recip(rhof);
                     const CT u = m0 * inv, v = m1 * inv, w = m2 * inv;
@@ -278,7 +302,7 @@ split_stage_kernel(Consts c, StageArgs s)
                 acc[f] = ocol[2][f];
                 ocol[2][f] = ocol[1][f];
                 ocol[1][f] = ocol[0][f];
-                ocol[0][f] = (double)pf[0][f];
+                ocol[0][f] = (double)pf[0][f][0];
             }
         };
 
@@ -611,15 +635,20 @@ hipError_t launch_sp(const Consts &c, const StageArgs &s, hipStream_t st)
     if constexpr (std::is_same<TIN, double>::value) {
         if (s.mode == 1) {
             if (s.diag_partial != nullptr)
-                hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, true, true>), grid, block, 0,
-                                   st, c, s);
+                hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, true, true, false>), grid, block,
+                                   0, st, c, s);
             else
-                hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, false, true>), grid, block, 0,
-                                   st, c, s);
+                hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, false, true, false>), grid, block,
+                                   0, st, c, s);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, false, false>), grid, block, 0, st, c, s);
+    if (c.nx % 2 == 0)
+        hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, false, false, true>), grid, block, 0, st,
+                           c, s);
+    else
+        hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, false, false, false>), grid, block, 0, st,
+                           c, s);
     return hipGetLastError();
 }
 
@@ -641,7 +670,7 @@ int resident_sp()
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per, reinterpret_cast<const void *>(&split_stage_kernel<BX, BY, TIN, TOUT, CT, false, false>),
+            &per, reinterpret_cast<const void *>(&split_stage_kernel<BX, BY, TIN, TOUT, CT, false, false, true>),
             2 * BX * BY, 0) != hipSuccess)
         return 0;
     return cus * (per > 0 ? per : 1);

@@ -140,10 +140,11 @@ def test_rk3_ragged_random(ns, algo):
     assert max(e) < TOL, e
 
 
-def test_tilings_match_oracle_and_zchunk_is_bitwise(ns):
+@pytest.mark.parametrize("n", [(37, 21, 19), (38, 21, 19)])
+def test_tilings_match_oracle_and_zchunk_is_bitwise(ns, n):
     """Every launch shape matches the oracle; for one tile shape the z-chunk
-    length changes nothing, bit for bit (a race or halo bug would show)."""
-    n = (37, 21, 19)
+    length changes nothing, bit for bit (a race or halo bug would show).
+    An even x extent also takes the two-group kernel's paired plane loads."""
     Q0 = synth.random_state(n[::-1], seed=3)
     ph = phys(n, mach=0.2)
     p = params(ns, n, mach=0.2)
