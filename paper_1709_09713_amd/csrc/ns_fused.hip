@@ -98,13 +98,20 @@ __device__ __forceinline__ float recip(float x)
 // SN / SN2 distinction of the minimal-storage section): 0 groups them by
 // equation, the momentum equations by velocity component; 1 groups them by
 // derivative direction.  Same terms, different association of the sums.
-template <int BX, int BY, typename TIN, typename TOUT, typename CT, bool DIAG, int ORD>
+//
+// PAIR (even nx; not with the FP32 stage-1 own-column loads): each load
+// slot covers two x-neighbours with one 2-wide load.  Pairs start at even x,
+// so with nx even they never straddle the periodic wrap.
+template <int BX, int BY, typename TIN, typename TOUT, typename CT, bool DIAG, int ORD, bool PAIR>
 __global__ void __launch_bounds__(BX * BY)
 fused_stage_kernel(Consts c, StageArgs s)
 {
     constexpr bool DEV = std::is_same<CT, float>::value;
+    static_assert(BX % 2 == 0, "pairs need an even tile width");
+    static_assert(!(PAIR && DEV && std::is_same<TIN, double>::value), "own-column loads are single");
     constexpr int HX = BX + 4, HY = BY + 4, HP = HX * HY, NT = BX * BY;
-    constexpr int NLOAD = (HP + NT - 1) / NT;
+    constexpr int PW = PAIR ? 2 : 1;                       // points per load slot
+    constexpr int NLOAD = (HP + PW * NT - 1) / (PW * NT);
     enum { L_RHO, L_M0, L_M1, L_M2, L_E, L_U, L_V, L_W, L_P, L_T, NF };
     enum { Z_RHO, Z_E, Z_U, Z_V, Z_W, NZ };
     __shared__ CT lds[2][NF][HP];
@@ -160,6 +167,13 @@ fused_stage_kernel(Consts c, StageArgs s)
                     lcell[r] = ly * HX + lx;
                 }
             }
+        } else if constexpr (PAIR) {
+            const int q = tid + r * NT;            // pair index
+            if (q < HP / 2) {
+                lx = 2 * (q % (HX / 2));
+                ly = q / (HX / 2);
+                lcell[r] = ly * HX + lx;
+            }
         } else {
             const int idx = tid + r * NT;
             if (idx < HP) {
@@ -189,7 +203,7 @@ fused_stage_kernel(Consts c, StageArgs s)
     CT qz[5][NZ];                 // ring: (rho, rhoE, u, v, w) of the own column
     CT qa[5], qb[5], qc[5];       // ring: D_x u + D_y v, D_x w, D_y w
     CT ra[5][NR];                 // ring: pending residuals (5) (+ omega_z)
-    TIN pf[NLOAD][5];             // next plane, prefetched
+    TIN pf[NLOAD][5][PW];         // next plane, prefetched
     double accpf[5];              // accumulator (or exact state) of the output point
     double ocol[3][5];            // exact state of the own column, three planes (OWN only)
 #pragma unroll
@@ -220,20 +234,31 @@ fused_stage_kernel(Consts c, StageArgs s)
         for (int r = 0; r < NLOAD; ++r) {
             const int64_t g = base + loff[r];
 #pragma unroll
-            for (int f = 0; f < 5; ++f) pf[r][f] = qin[g + f * N];
+            for (int f = 0; f < 5; ++f) {
+                if constexpr (PAIR) {
+                    typedef TIN pair_t __attribute__((ext_vector_type(2)));
+                    const pair_t v = *(const pair_t *)(qin + g + f * N);
+                    pf[r][f][0] = v.x;
+                    pf[r][f][1] = v.y;
+                } else {
+                    pf[r][f][0] = qin[g + f * N];
+                }
+            }
         }
     };
     // conserved (pf) -> primitives -> LDS buffer b
     auto stage_plane = [&](int b) {
 #pragma unroll
-        for (int r = 0; r < NLOAD; ++r) {
-            const int idx = lcell[r];
-            if (idx >= 0) {
-                const CT rho = to_ct<TIN, CT>(pf[r][0], c.rho_ref);
-                const CT m0 = to_ct<TIN, CT>(pf[r][1], 0.0);
-                const CT m1 = to_ct<TIN, CT>(pf[r][2], 0.0);
-                const CT m2 = to_ct<TIN, CT>(pf[r][3], 0.0);
-                const CT E = to_ct<TIN, CT>(pf[r][4], c.rhoE_ref);
+        for (int r = 0; r < NLOAD; ++r)
+#pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            const int idx = lcell[r] + j;
+            if (lcell[r] >= 0) {
+                const CT rho = to_ct<TIN, CT>(pf[r][0][j], c.rho_ref);
+                const CT m0 = to_ct<TIN, CT>(pf[r][1][j], 0.0);
+                const CT m1 = to_ct<TIN, CT>(pf[r][2][j], 0.0);
+                const CT m2 = to_ct<TIN, CT>(pf[r][3][j], 0.0);
+                const CT E = to_ct<TIN, CT>(pf[r][4][j], c.rhoE_ref);
                 const CT rhof = DEV ? CT(1) + rho : rho;
                 const CT inv = recip(rhof);
                 const CT u = m0 * inv, v = m1 * inv, w = m2 * inv;
@@ -261,7 +286,7 @@ fused_stage_kernel(Consts c, StageArgs s)
         for (int f = 0; f < 5; ++f) {
             ocol[2][f] = ocol[1][f];
             ocol[1][f] = ocol[0][f];
-            ocol[0][f] = (double)pf[0][f];
+            ocol[0][f] = (double)pf[0][f][0];
         }
     };
 
@@ -603,15 +628,27 @@ static hipError_t launch_o(const Consts &c, const StageArgs &s, hipStream_t st)
     dim3 grid((c.nx + BX - 1) / BX, (c.ny + BY - 1) / BY, (c.nz + s.zchunk - 1) / s.zchunk);
     // per-step diagnostics are only taken in stage 1, which reads the
     // double state
+    // paired plane loads need an even x extent; the FP32 stage-1 kernel
+    // loads single points (own-column accumulator)
+    constexpr bool CAN_PAIR = !(std::is_same<CT, float>::value && std::is_same<TIN, double>::value);
+    const bool pair = CAN_PAIR && c.nx % 2 == 0;
     if constexpr (std::is_same<TIN, double>::value) {
         if (s.diag_partial != nullptr && s.mode == 1) {
-            hipLaunchKernelGGL((fused_stage_kernel<BX, BY, TIN, TOUT, CT, true, ORD>), grid, block, 0,
-                               st, c, s);
+            if (pair)
+                hipLaunchKernelGGL((fused_stage_kernel<BX, BY, TIN, TOUT, CT, true, ORD, CAN_PAIR>), grid,
+                                   block, 0, st, c, s);
+            else
+                hipLaunchKernelGGL((fused_stage_kernel<BX, BY, TIN, TOUT, CT, true, ORD, false>), grid, block,
+                                   0, st, c, s);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((fused_stage_kernel<BX, BY, TIN, TOUT, CT, false, ORD>), grid, block, 0, st, c,
-                       s);
+    if (pair)
+        hipLaunchKernelGGL((fused_stage_kernel<BX, BY, TIN, TOUT, CT, false, ORD, CAN_PAIR>), grid, block, 0,
+                           st, c, s);
+    else
+        hipLaunchKernelGGL((fused_stage_kernel<BX, BY, TIN, TOUT, CT, false, ORD, false>), grid, block, 0, st,
+                           c, s);
     return hipGetLastError();
 }
 
@@ -667,7 +704,7 @@ static int resident_t()
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per, reinterpret_cast<const void *>(&fused_stage_kernel<BX, BY, TIN, TOUT, CT, false, 0>),
+            &per, reinterpret_cast<const void *>(&fused_stage_kernel<BX, BY, TIN, TOUT, CT, false, 0, false>),
             BX * BY, 0) != hipSuccess)
         return 0;
     return cus * (per > 0 ? per : 1);
