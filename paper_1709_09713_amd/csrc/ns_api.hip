@@ -82,8 +82,8 @@ static void choose_config(const Consts &c, ns_precision prec, int tile_in, int z
     int z = tile_in >= 0 ? zchunk_in : g_zchunk.load();
     if (zchunk_in > 0) z = zchunk_in;
     // defaults measured on MI355X: FP64 runs fastest with the two-group
-    // 32x8 kernel at every cube from 128^3 to 512^3, FP32 storage with the
-    // one-thread 32x8 kernel
+    // 32x8 kernel on cubes from 128^3 to 512^3 (384^3: within 1% of the
+    // one-thread 16x8 kernel), FP32 storage with the one-thread 32x8 kernel
     if (t < 0 || t >= TILE_COUNT) t = (prec == NS_FP64) ? TILE_32x8_2G : TILE_32x8;
     if (z <= 0) z = default_zchunk(c, prec, t);
     if (z < kMinZChunk) z = kMinZChunk;
