@@ -67,6 +67,25 @@ def random_state(shape, seed: int, *, energy_mean: float = 180.0,
     return Q
 
 
+def resting_density_mode(shape, direction: int, mode: int, eps: float,
+                         energy: float):
+    """Conserved state Q[5, nz, ny, nx] of a fluid at rest with a density
+    wave along one direction: rho = 1 / (1 + eps cos(theta)),
+    theta = 2 pi mode i_d / n_d, zero momentum and uniform rho E = energy.
+    (The fluid is at rest and, for a uniform rho E, at uniform pressure, so
+    only heat conduction acts on it.)"""
+    nz, ny, nx = shape
+    n_d = (nx, ny, nz)[direction]
+    idx = np.arange(n_d) * (2 * np.pi * mode / n_d)
+    bshape = [1, 1, 1]
+    bshape[2 - direction] = n_d
+    theta = np.broadcast_to(idx.reshape(bshape), shape)
+    Q = np.zeros((5,) + tuple(shape))
+    Q[0] = 1.0 / (1.0 + eps * np.cos(theta))
+    Q[4] = energy
+    return Q
+
+
 def sample_points(shape, count: int, seed: int):
     """``count`` distinct linear point indices of a grid of ``shape``
     (nz, ny, nx), always including the eight corners (wrap-around cases)."""

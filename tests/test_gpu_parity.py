@@ -473,3 +473,31 @@ def test_residual_is_fourth_order_on_gpu(ns, algo):
         ratio = e1 / e2
         print(f"{algo} field {f}: |R32-R64| {e1:.3e} |R64-R128| {e2:.3e} ratio {ratio:.2f}", flush=True)
         assert 12.0 < ratio < 20.0, (f, ratio)
+
+
+@pytest.mark.parametrize("algo", ["fused", "stored", "some"])
+@pytest.mark.parametrize("case", [0, 1])
+def test_heat_conduction_closed_form_on_gpu(ns, algo, case):
+    """The resting temperature wave of the oracle pin (see
+    closed_forms.heat_mode_expected), on all three classes and in every
+    direction: only the heat-conduction term of the energy equation
+    survives, with kappa = 1/((gamma-1) M^2 Pr Re) and T from eq.
+    (Tinprimitive).  Mass and momentum residuals are zero to the rounding of
+    the pressure-gradient stencil (terms of size p / h cancel)."""
+    from closed_forms import HEAT_CASES, heat_mode_expected
+    n, length, g, pr, re, mach = HEAT_CASES[case]
+    eps = 0.05
+    energy = 1.0 / (g * (g - 1.0) * mach ** 2)
+    p = ns.make_params(n, length=length, gamma=g, prandtl=pr, reynolds=re, mach=mach)
+    pres = (g - 1.0) * energy
+    hmin = min(L / k for L, k in zip(length, n))
+    for d in range(3):
+        for m in (1, 2):
+            Q = synth.resting_density_mode(n[::-1], d, m, eps, energy)
+            R = gpu_residual(ns, p, ns.ALGOS[algo], Q)
+            want = heat_mode_expected(HEAT_CASES[case], d, m, eps, energy)
+            e = float(np.abs(R[4] - want).max() / np.abs(want).max())
+            print(f"heat {algo} case {case} d={d} m={m}: R_E rel {e:.2e} "
+                  f"max|R_rho,m| {np.abs(R[:4]).max():.1e}", flush=True)
+            assert e < TOL, (d, m, e)
+            assert np.abs(R[:4]).max() < 1e-12 * pres / hmin, (d, m)

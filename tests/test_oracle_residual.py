@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import synth
+from closed_forms import HEAT_CASES, heat_mode_expected
 from oracle import numpy_ref
 
 INF = float("inf")
@@ -51,6 +52,26 @@ def test_uniform_state_has_zero_residual(orc):
     Q[0], Q[1], Q[2], Q[3], Q[4] = 1.3, 0.4, -0.2, 0.7, 200.0
     R = orc.residual(ph, Q)
     assert np.abs(R).max() < 1e-12
+
+
+@pytest.mark.parametrize("case", [0, 1])
+@pytest.mark.parametrize("d", [0, 1, 2])
+@pytest.mark.parametrize("m", [1, 2])
+def test_heat_conduction_closed_form(orc, case, d, m):
+    """A resting fluid at uniform pressure with a temperature wave along
+    x_d: mass and momentum residuals are exactly zero and the energy
+    residual is the heat-conduction term alone, in closed form (see
+    heat_mode_expected).  Pins kappa (every factor: gamma - 1, M^2, Pr, Re),
+    T from eq. (Tinprimitive), the direction of each D2_j T and the sign."""
+    n, length, g, pr, re, mach = HEAT_CASES[case]
+    eps = 0.05
+    energy = 1.0 / (g * (g - 1.0) * mach ** 2)      # p = 1 / (gamma M^2)
+    ph = orc.Physics(n=n, length=length, gamma=g, prandtl=pr, reynolds=re, mach=mach)
+    Q = synth.resting_density_mode(n[::-1], d, m, eps, energy)
+    R = orc.residual(ph, Q)
+    assert np.all(R[:4] == 0.0)
+    want = heat_mode_expected(HEAT_CASES[case], d, m, eps, energy)
+    assert _rel(R[4], want) < 1e-12
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
