@@ -20,7 +20,8 @@
  *     5*nx*ny*nz doubles in device memory.  Point (i,j,k) is at
  *     (i*hx, j*hy, k*hz), h = length / n.
  *   - Pointers named state, Q, R and work are DEVICE pointers owned by the
- *     caller; the library keeps none of them after returning, except a
+ *     caller (state, Q and R 16-byte aligned, else NS_ERR_ARG: the kernels
+ *     load pairs of doubles; work 256-byte aligned; diag_dev 8-byte); the library keeps none of them after returning, except a
  *     batch, which keeps its members' state and work pointers until they
  *     are removed (ns_batch_add).  out_host is a host pointer.
  *   - stream is a hipStream_t (NULL = the default stream).  Calls are
@@ -51,6 +52,8 @@ typedef enum {
     NS_ERR_WORKSPACE = -3,   /* work_bytes smaller than ns_workspace_bytes() or misaligned */
     NS_ERR_DEVICE = -4,      /* a HIP call failed */
     NS_ERR_NONFINITE = -5,   /* diagnostics found a NaN or infinity */
+    NS_ERR_NOMEM = -6,       /* a device or host allocation failed (batch creation only:
+                                the single-solve calls allocate nothing) */
     NS_ERR_UNSUPPORTED = -7  /* valid but not provided (stored or intermediate-storage
                                 class in FP32 storage) */
 } ns_status;
@@ -127,8 +130,11 @@ ns_status tgv_init(const ns_params *p, double *state, void *stream);
 /* One evaluation of the residual R(Q) (the right-hand sides of the mass,
  * momentum and energy equations, discretised with (fd)/(sd) and periodic
  * boundaries), FP64, with the chosen algorithm class.  Q and R are device
- * arrays of 5*N doubles and must not overlap; Q is not modified.  work
- * needs ns_workspace_bytes(p, algo, NS_FP64) bytes. */
+ * arrays of 5*N doubles and must not overlap; Q is not modified.  The
+ * stored and intermediate-storage classes need work of
+ * ns_workspace_bytes(p, algo, NS_FP64) bytes; the fused class keeps every
+ * derivative on chip and uses no scratch, so with NS_ALGO_FUSED work and
+ * work_bytes are ignored (NULL / 0 allowed). */
 ns_status ns_residual(const ns_params *p, ns_algo algo, const double *Q,
                       double *R, void *work, size_t work_bytes, void *stream);
 
@@ -154,7 +160,9 @@ ns_status diagnostics(const ns_params *p, const double *state,
                       ns_diag *out_host, void *work, size_t work_bytes,
                       void *stream);
 
-/* Launch shape of the fused kernel, process-wide.  tile selects the
+/* Launch shape of the fused kernel for later calls made by the calling
+ * thread (each thread keeps its own setting; a batch member fixes its shape
+ * when it is added).  tile selects the
  * (x, y) column tile of one block: 0 = 32x8, 1 = 16x16, 2 = 64x4,
  * 3 = 32x16, 4 = 16x8, 5 = 32x4, 6 = 16x4, 7 = 8x8 (threads = product, one
  * z column each); 8 = 16x8, 9 = 32x8, 10 = 16x4 with two threads per
@@ -169,16 +177,17 @@ ns_status diagnostics(const ns_params *p, const double *state,
  * instances and may differ at the rounding level (the compiler can contract
  * a multiply-add differently); per-step diagnostics also differ in the
  * order of their sums.
- * Returns NS_ERR_ARG for out-of-range values.  Not thread-safe with
- * concurrent launches that expect a different shape. */
+ * Returns NS_ERR_ARG for out-of-range values. */
 ns_status ns_set_fused_config(int32_t tile, int32_t zchunk);
 
-/* The (tile, zchunk) the fused kernel would use for p and prec right now. */
+/* The (tile, zchunk) the fused kernel would use for p and prec in a call
+ * made now by the calling thread. */
 ns_status ns_get_fused_config(const ns_params *p, ns_precision prec,
                               int32_t *tile, int32_t *zchunk);
 
-/* Evaluation order of the fused kernel's in-plane residual terms,
- * process-wide (the SN / SN2 distinction of the minimal-storage section):
+/* Evaluation order of the fused kernel's in-plane residual terms for later
+ * calls of the calling thread (the SN / SN2 distinction of the
+ * minimal-storage section):
  * 0 = grouped by equation, the momentum equations by velocity component
  * (default); 1 = grouped by derivative direction (all x derivatives of all
  * equations, then all y derivatives).  The two orders sum the same terms
@@ -188,7 +197,7 @@ ns_status ns_get_fused_config(const ns_params *p, ns_precision prec,
  * other tile.  NS_ERR_ARG for other values. */
 ns_status ns_set_fused_order(int32_t order);
 
-/* The current evaluation order (0 or 1). */
+/* The calling thread's evaluation order (0 or 1). */
 int32_t ns_get_fused_order(void);
 
 /* ------------------------------------------------------------------------
@@ -228,8 +237,9 @@ typedef struct {
  * precision prec over nstreams (1..8) internal streams; with_diagnostics
  * != 0 computes each member's diagnostics of the state at the start of
  * every step it runs (last one readable with ns_batch_poll).  Allocates
- * streams, events and the diagnostics array (NS_ERR_DEVICE on failure);
- * NS_ERR_ARG for bad arguments. */
+ * streams, events and the diagnostics array (NS_ERR_NOMEM if an allocation
+ * runs out of memory, NS_ERR_DEVICE for other HIP failures); NS_ERR_ARG for
+ * bad arguments. */
 ns_status ns_batch_create(int32_t max_instances, ns_precision prec,
                           int32_t nstreams, int32_t with_diagnostics,
                           ns_batch **out);

@@ -22,6 +22,7 @@ NS_ERR_SHAPE = -2
 NS_ERR_WORKSPACE = -3
 NS_ERR_DEVICE = -4
 NS_ERR_NONFINITE = -5
+NS_ERR_NOMEM = -6
 NS_ERR_UNSUPPORTED = -7
 
 NS_ALGO_STORED = 0
@@ -75,10 +76,14 @@ EXPORTS = ("ns_status_string", "ns_state_bytes", "ns_workspace_bytes",
            "ns_batch_step", "ns_batch_set_graphs", "ns_batch_poll", "ns_batch_info")
 
 
+_STATUS_TEXT = {NS_ERR_ARG: "NS_ERR_ARG: invalid argument"}
+
+
 class NativeError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
-        super().__init__(f"{where}: {status_string(status)} ({status})")
+        text = _STATUS_TEXT.get(status) if _lib is None else None
+        super().__init__(f"{where}: {text or status_string(status)} ({status})")
 
 
 _lib = None
@@ -157,12 +162,32 @@ def make_params(n, length=None, gamma=1.4, prandtl=0.71, reynolds=1600.0,
     return p
 
 
-def _ptr(x) -> int | None:
+def _ptr(x, where: str = "buffer", dtype: str | None = None, min_bytes: int = 0) -> int | None:
+    """Device address of x: an int is taken as a raw device address (the C
+    side still checks null and alignment); a tensor must be a contiguous CUDA
+    tensor of ``dtype`` (e.g. "float64") holding at least ``min_bytes`` bytes,
+    else NativeError(NS_ERR_ARG) is raised before anything reaches the
+    library."""
     if x is None:
         return None
     if isinstance(x, int):
         return x
+    if not hasattr(x, "data_ptr"):
+        raise NativeError(NS_ERR_ARG, f"{where}: expected a device tensor or an address")
+    if dtype is not None and str(x.dtype) != "torch." + dtype:
+        raise NativeError(NS_ERR_ARG, f"{where}: dtype {x.dtype}, expected {dtype}")
+    if not x.is_contiguous():
+        raise NativeError(NS_ERR_ARG, f"{where}: tensor is not contiguous")
+    nbytes = x.numel() * x.element_size()
+    if nbytes < min_bytes:
+        raise NativeError(NS_ERR_ARG, f"{where}: {nbytes} bytes, needs {min_bytes}")
+    if x.device.type != "cuda":
+        raise NativeError(NS_ERR_ARG, f"{where}: tensor on {x.device}, expected a CUDA device")
     return x.data_ptr()
+
+
+def _nbytes(x) -> int:
+    return x.numel() * x.element_size()
 
 
 def _stream(stream) -> int | None:
@@ -182,32 +207,40 @@ def ns_workspace_bytes(p: ns_params, algo: int, prec: int = NS_FP64) -> int:
 
 
 def tgv_init(p: ns_params, state, stream=None):
-    _check(lib().tgv_init(ctypes.byref(p), _ptr(state), _stream(stream)), "tgv_init")
+    st = _ptr(state, "tgv_init state", "float64", ns_state_bytes(p))
+    _check(lib().tgv_init(ctypes.byref(p), st, _stream(stream)), "tgv_init")
 
 
 def ns_residual(p: ns_params, algo: int, Q, R, work=None, work_bytes: int = 0,
                 stream=None):
     if work is not None and work_bytes == 0 and not isinstance(work, int):
-        work_bytes = work.numel() * work.element_size()
-    _check(lib().ns_residual(ctypes.byref(p), int(algo), _ptr(Q), _ptr(R), _ptr(work),
-                             work_bytes, _stream(stream)), "ns_residual")
+        work_bytes = _nbytes(work)
+    sb = ns_state_bytes(p)
+    q = _ptr(Q, "ns_residual Q", "float64", sb)
+    r = _ptr(R, "ns_residual R", "float64", sb)
+    w = _ptr(work, "ns_residual work", None, work_bytes)
+    _check(lib().ns_residual(ctypes.byref(p), int(algo), q, r, w, work_bytes, _stream(stream)),
+           "ns_residual")
 
 
 def rk3_step(p: ns_params, algo: int, prec: int, dt: float, nsteps: int, state,
              work, work_bytes: int = 0, diag_dev=None, stream=None):
     if work_bytes == 0 and work is not None and not isinstance(work, int):
-        work_bytes = work.numel() * work.element_size()
+        work_bytes = _nbytes(work)
+    st = _ptr(state, "rk3_step state", "float64", ns_state_bytes(p))
+    w = _ptr(work, "rk3_step work", None, work_bytes)
+    d = _ptr(diag_dev, "rk3_step diag_dev", "float64", 64 * max(int(nsteps), 0))
     _check(lib().rk3_step(ctypes.byref(p), int(algo), int(prec), float(dt), int(nsteps),
-                          _ptr(state), _ptr(work), work_bytes, _ptr(diag_dev),
-                          _stream(stream)), "rk3_step")
+                          st, w, work_bytes, d, _stream(stream)), "rk3_step")
 
 
 def diagnostics(p: ns_params, state, work, work_bytes: int = 0, stream=None) -> dict:
     if work_bytes == 0 and work is not None and not isinstance(work, int):
-        work_bytes = work.numel() * work.element_size()
+        work_bytes = _nbytes(work)
+    sp = _ptr(state, "diagnostics state", "float64", ns_state_bytes(p))
+    w = _ptr(work, "diagnostics work", None, work_bytes)
     out = ns_diag()
-    st = lib().diagnostics(ctypes.byref(p), _ptr(state), ctypes.byref(out), _ptr(work),
-                           work_bytes, _stream(stream))
+    st = lib().diagnostics(ctypes.byref(p), sp, ctypes.byref(out), w, work_bytes, _stream(stream))
     if st not in (NS_OK, NS_ERR_NONFINITE):
         _check(st, "diagnostics")
     d = out.as_dict()
@@ -252,9 +285,10 @@ def ns_batch_destroy(handle: int):
 def ns_batch_add(handle: int, p: ns_params, dt: float, steps: int, state, work,
                  work_bytes: int = 0, tile: int = -1, zchunk: int = 0) -> int:
     if work_bytes == 0 and not isinstance(work, int):
-        work_bytes = work.numel() * work.element_size()
-    inst = ns_instance(p, float(dt), int(steps), int(tile), int(zchunk), _ptr(state), _ptr(work),
-                       work_bytes)
+        work_bytes = _nbytes(work)
+    st = _ptr(state, "ns_batch_add state", "float64", ns_state_bytes(p))
+    w = _ptr(work, "ns_batch_add work", None, work_bytes)
+    inst = ns_instance(p, float(dt), int(steps), int(tile), int(zchunk), st, w, work_bytes)
     slot = ctypes.c_int32()
     _check(lib().ns_batch_add(handle, ctypes.byref(inst), ctypes.byref(slot)), "ns_batch_add")
     return slot.value

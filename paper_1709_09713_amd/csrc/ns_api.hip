@@ -1,7 +1,6 @@
 // ns_api.hip -- the C ABI (include/ns_tgv.h): argument validation,
 // workspace layout and the per-step launch sequence of the three algorithm
 // classes.  Every call validates first and enqueues nothing on failure.
-#include <atomic>
 #include <cmath>
 #include <cstring>
 
@@ -39,9 +38,12 @@ Consts make_consts(const ns_params *p)
 
 
 constexpr int kMinZChunk = 1;
-static std::atomic<int> g_tile{-1};
-static std::atomic<int> g_zchunk{0};
-static std::atomic<int> g_order{0};
+// Launch settings of ns_set_fused_config / ns_set_fused_order: one copy per
+// calling thread, so threads that drive solves of different shapes do not
+// see each other's settings.
+static thread_local int g_tile = -1;
+static thread_local int g_zchunk = 0;
+static thread_local int g_order = 0;
 
 // Default z-chunk: a block marches zchunk + 4 planes (+ 5 for the
 // two-group tiles; padded to the unroll of 5), and the grid runs in ceil(blocks / resident) rounds of resident
@@ -74,12 +76,12 @@ static int default_zchunk(const Consts &c, ns_precision prec, int tile)
 }
 
 // Launch shape: an explicit tile (>= 0) / zchunk (> 0) wins, else the
-// process-wide setting of ns_set_fused_config, else the default.
+// calling thread's setting of ns_set_fused_config, else the default.
 static void choose_config(const Consts &c, ns_precision prec, int tile_in, int zchunk_in, int *tile,
                           int *zchunk)
 {
-    int t = tile_in >= 0 ? tile_in : g_tile.load();
-    int z = tile_in >= 0 ? zchunk_in : g_zchunk.load();
+    int t = tile_in >= 0 ? tile_in : g_tile;
+    int z = tile_in >= 0 ? zchunk_in : g_zchunk;
     if (zchunk_in > 0) z = zchunk_in;
     // defaults measured on MI355X: FP64 runs fastest with the two-group
     // 32x8 kernel on cubes from 128^3 to 512^3 (384^3: within 1% of the
@@ -181,6 +183,11 @@ static ns_status check_work(const void *work, size_t have, size_t need)
     return NS_OK;
 }
 
+// State, Q and R arrays must be 16-byte aligned (the stage kernels load
+// x-neighbour pairs of doubles with one 16-byte access); diagnostics
+// records 8-byte aligned.
+static bool aligned(const void *ptr, uintptr_t a) { return ((uintptr_t)ptr & (a - 1)) == 0; }
+
 template <typename T>
 static T *at(void *work, size_t off)
 {
@@ -192,7 +199,7 @@ ns_status make_fused_plan(const ns_params *p, ns_precision prec, int tile, int z
 {
     ns_status st = check_params(p);
     if (st != NS_OK) return st;
-    if (!valid_prec(prec) || !state || !out) return NS_ERR_ARG;
+    if (!valid_prec(prec) || !state || !out || !aligned(state, 16)) return NS_ERR_ARG;
     if (tile < -1 || tile >= TILE_COUNT || zchunk < 0 || (zchunk > 0 && zchunk < kMinZChunk))
         return NS_ERR_ARG;
     const Consts c = make_consts(p);
@@ -203,7 +210,7 @@ ns_status make_fused_plan(const ns_params *p, ns_precision prec, int tile, int z
     f.c = c;
     f.prec = prec;
     choose_config(c, prec, tile, zchunk, &f.tile, &f.zchunk);
-    f.order = g_order.load();
+    f.order = g_order;
     if (!fused_order_supported(f.tile, f.order)) return NS_ERR_UNSUPPORTED;
     f.nblk = fused_num_blocks(c, f.tile, f.zchunk);
     f.state = state;
@@ -272,6 +279,7 @@ const char *ns_status_string(ns_status s)
     case NS_ERR_WORKSPACE: return "NS_ERR_WORKSPACE: workspace too small or misaligned";
     case NS_ERR_DEVICE: return "NS_ERR_DEVICE: HIP error";
     case NS_ERR_NONFINITE: return "NS_ERR_NONFINITE: non-finite diagnostics";
+    case NS_ERR_NOMEM: return "NS_ERR_NOMEM: device memory allocation failed";
     case NS_ERR_UNSUPPORTED: return "NS_ERR_UNSUPPORTED: combination not provided";
     }
     return "unknown ns_status";
@@ -294,19 +302,19 @@ ns_status ns_set_fused_config(int32_t tile, int32_t zchunk)
 {
     if (tile < -1 || tile >= TILE_COUNT || zchunk < 0) return NS_ERR_ARG;
     if (zchunk > 0 && zchunk < kMinZChunk) return NS_ERR_ARG;
-    g_tile.store(tile);
-    g_zchunk.store(zchunk);
+    g_tile = tile;
+    g_zchunk = zchunk;
     return NS_OK;
 }
 
 ns_status ns_set_fused_order(int32_t order)
 {
     if (order != 0 && order != 1) return NS_ERR_ARG;
-    g_order.store(order);
+    g_order = order;
     return NS_OK;
 }
 
-int32_t ns_get_fused_order(void) { return g_order.load(); }
+int32_t ns_get_fused_order(void) { return g_order; }
 
 ns_status ns_get_fused_config(const ns_params *p, ns_precision prec, int32_t *tile,
                               int32_t *zchunk)
@@ -325,7 +333,7 @@ ns_status tgv_init(const ns_params *p, double *state, void *stream)
 {
     ns_status st = check_params(p);
     if (st != NS_OK) return st;
-    if (!state) return NS_ERR_ARG;
+    if (!state || !aligned(state, 16)) return NS_ERR_ARG;
     const Consts c = make_consts(p);
     NS_HIP_OK(launch_tgv_init(c, p, state, (hipStream_t)stream));
     return NS_OK;
@@ -336,7 +344,7 @@ ns_status ns_residual(const ns_params *p, ns_algo algo, const double *Q, double 
 {
     ns_status st = check_params(p);
     if (st != NS_OK) return st;
-    if (!valid_algo(algo) || !Q || !R) return NS_ERR_ARG;
+    if (!valid_algo(algo) || !Q || !R || !aligned(Q, 16) || !aligned(R, 16)) return NS_ERR_ARG;
     const Consts c = make_consts(p);
     const size_t n5b = 5 * (size_t)c.N * sizeof(double);
     if ((const char *)Q < (const char *)R + n5b && (const char *)R < (const char *)Q + n5b)
@@ -345,7 +353,7 @@ ns_status ns_residual(const ns_params *p, ns_algo algo, const double *Q, double 
     if (algo == NS_ALGO_FUSED) {
         int tile, zc;
         choose_config(c, NS_FP64, &tile, &zc);
-        const int order = g_order.load();
+        const int order = g_order;
         if (!fused_order_supported(tile, order)) return NS_ERR_UNSUPPORTED;
         StageArgs a = {};
         a.order = order;
@@ -372,7 +380,8 @@ ns_status rk3_step(const ns_params *p, ns_algo algo, ns_precision prec, double d
 {
     ns_status st = check_params(p);
     if (st != NS_OK) return st;
-    if (!valid_algo(algo) || !valid_prec(prec) || !state) return NS_ERR_ARG;
+    if (!valid_algo(algo) || !valid_prec(prec) || !state || !aligned(state, 16)) return NS_ERR_ARG;
+    if (diag_dev && !aligned(diag_dev, 8)) return NS_ERR_ARG;
     if (!std::isfinite(dt) || !(dt > 0.0) || nsteps < 0) return NS_ERR_ARG;
     if (algo != NS_ALGO_FUSED && prec != NS_FP64) return NS_ERR_UNSUPPORTED;
     const Consts c = make_consts(p);
@@ -434,7 +443,7 @@ ns_status diagnostics(const ns_params *p, const double *state, ns_diag *out_host
 {
     ns_status st = check_params(p);
     if (st != NS_OK) return st;
-    if (!state || !out_host) return NS_ERR_ARG;
+    if (!state || !out_host || !aligned(state, 16)) return NS_ERR_ARG;
     const Consts c = make_consts(p);
     const Layout L = layout(c, NS_ALGO_FUSED, NS_FP64);
     st = check_work(work, work_bytes, diag_bytes(c));

@@ -160,7 +160,7 @@ ns_status ns_batch_create(int32_t max_instances, ns_precision prec, int32_t nstr
     if (prec != NS_FP64 && prec != NS_FP32_STORE) return NS_ERR_ARG;
     if (nstreams < 1 || nstreams > kMaxStreams) return NS_ERR_ARG;
     ns_batch *b = new (std::nothrow) ns_batch();
-    if (!b) return NS_ERR_DEVICE;
+    if (!b) return NS_ERR_NOMEM;
     b->max_inst = max_instances;
     b->nstreams = nstreams;
     b->prec = prec;
@@ -172,15 +172,17 @@ ns_status ns_batch_create(int32_t max_instances, ns_precision prec, int32_t nstr
         ok = hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming) == hipSuccess;
     }
+    ns_status fail = NS_ERR_DEVICE;
     if (ok && b->diag) {
         const size_t bytes = (size_t)max_instances * sizeof(ns_diag);
-        ok = hipMalloc((void **)&b->d_diag, bytes) == hipSuccess &&
-             hipMemset(b->d_diag, 0, bytes) == hipSuccess;
+        const hipError_t e = hipMalloc((void **)&b->d_diag, bytes);
+        if (e == hipErrorOutOfMemory) fail = NS_ERR_NOMEM;
+        ok = e == hipSuccess && hipMemset(b->d_diag, 0, bytes) == hipSuccess;
     }
     if (!ok) {
         destroy(b);
         delete b;
-        return NS_ERR_DEVICE;
+        return fail;
     }
     *out = b;
     return NS_OK;

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_status_strings():
-    for code in (0, -1, -2, -3, -4, -5, -7):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert ns.status_string(code).startswith("NS_")
 
 
@@ -209,3 +209,91 @@ def test_fused_order_validation():
     finally:
         ns.ns_set_fused_config(-1, 0)
         ns.ns_set_fused_order(0)
+
+
+def test_c_abi_rejects_misaligned_pointers():
+    """State, Q and R must be 16-byte aligned (pairs of doubles are loaded
+    with one access) and per-step diagnostics records 8-byte aligned; the
+    check comes before any enqueue."""
+    p = ns.make_params(16)
+    wb = ns.ns_workspace_bytes(p, ns.NS_ALGO_FUSED, ns.NS_FP64)
+    calls = [
+        lambda: ns.tgv_init(p, 0x1008),
+        lambda: ns.rk3_step(p, ns.NS_ALGO_FUSED, ns.NS_FP64, 1e-3, 1, 0x1008, 0x100000, wb),
+        lambda: ns.rk3_step(p, ns.NS_ALGO_FUSED, ns.NS_FP64, 1e-3, 1, 0x1000, 0x100000, wb,
+                            diag_dev=0x2004),
+        lambda: ns.ns_residual(p, ns.NS_ALGO_FUSED, 0x100008, 0x10000000),
+        lambda: ns.ns_residual(p, ns.NS_ALGO_FUSED, 0x100000, 0x10000008),
+        lambda: ns.diagnostics(p, 0x1008, 0x100000, wb),
+    ]
+    for i, call in enumerate(calls):
+        with pytest.raises(ns.NativeError) as e:
+            call()
+        assert e.value.status == ns.NS_ERR_ARG, i
+
+
+def test_binding_rejects_bad_tensors_before_the_library():
+    """The Python binding refuses tensors the kernels would read or write
+    past: wrong dtype, not contiguous, too small, or not on a GPU."""
+    import torch
+    p = ns.make_params(16)
+    n5 = 5 * 16 ** 3
+    wb = ns.ns_workspace_bytes(p, ns.NS_ALGO_FUSED, ns.NS_FP64)
+    good_work = 0x100000
+    bad_states = [
+        torch.zeros(n5, dtype=torch.float32),                  # dtype
+        torch.zeros((2 * n5,), dtype=torch.float64)[::2],      # not contiguous
+        torch.zeros(n5 - 1, dtype=torch.float64),              # too small
+        torch.zeros(n5, dtype=torch.float64),                  # host memory
+    ]
+    for st in bad_states:
+        with pytest.raises(ns.NativeError) as e:
+            ns.rk3_step(p, ns.NS_ALGO_FUSED, ns.NS_FP64, 1e-3, 1, st, good_work, wb)
+        assert e.value.status == ns.NS_ERR_ARG
+        with pytest.raises(ns.NativeError):
+            ns.tgv_init(p, st)
+        with pytest.raises(ns.NativeError):
+            ns.ns_residual(p, ns.NS_ALGO_FUSED, st, 0x10000000)
+        with pytest.raises(ns.NativeError):
+            ns.diagnostics(p, st, good_work, wb)
+    # workspace smaller than the bytes claimed for it, per-step diagnostics
+    # with fewer records than steps
+    with pytest.raises(ns.NativeError):
+        ns.rk3_step(p, ns.NS_ALGO_FUSED, ns.NS_FP64, 1e-3, 1, 0x1000,
+                    torch.zeros(16, dtype=torch.uint8), wb)
+    with pytest.raises(ns.NativeError):
+        ns.rk3_step(p, ns.NS_ALGO_FUSED, ns.NS_FP64, 1e-3, 3, 0x1000, good_work, wb,
+                    diag_dev=torch.zeros((2, 8), dtype=torch.float64))
+
+
+def test_launch_settings_are_per_thread():
+    """ns_set_fused_config / ns_set_fused_order apply to the calling thread
+    only: two threads with different settings, interleaved, each see their
+    own, and the main thread keeps the default."""
+    import threading
+    p = ns.make_params(64)
+    default = ns.ns_get_fused_config(p)
+    barrier = threading.Barrier(2)
+    seen = {}
+
+    def worker(name, tile, zchunk, order):
+        ns.ns_set_fused_config(tile, zchunk)
+        ns.ns_set_fused_order(order)
+        got = []
+        for _ in range(50):
+            barrier.wait()
+            got.append((ns.ns_get_fused_config(p), ns.ns_get_fused_order()))
+        seen[name] = got
+        ns.ns_set_fused_config(-1, 0)
+        ns.ns_set_fused_order(0)
+
+    ts = [threading.Thread(target=worker, args=("a", 4, 6, 1)),
+          threading.Thread(target=worker, args=("b", 9, 11, 0))]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert set(seen["a"]) == {((4, 6), 1)}
+    assert set(seen["b"]) == {((9, 11), 0)}
+    assert ns.ns_get_fused_config(p) == default
+    assert ns.ns_get_fused_order() == 0
