@@ -160,6 +160,18 @@ ns_status diagnostics(const ns_params *p, const double *state,
                       ns_diag *out_host, void *work, size_t work_bytes,
                       void *stream);
 
+/* Measurement support, not part of the method: move exactly the HBM bytes
+ * of fused RK stage `stage` (1..3) in FP64 -- stage 1 reads state and writes
+ * the next stage input and the accumulator, stage 2 reads both and writes
+ * both, stage 3 reads both and writes state, the same buffers rk3_step uses
+ * in work -- with a pointwise update instead of the residual.  Its rate is
+ * the ceiling that the memory system allows the fused stage kernel's access
+ * pattern.  work needs ns_workspace_bytes(p, NS_ALGO_FUSED, NS_FP64) bytes;
+ * state and the workspace buffers are overwritten with meaningless values.
+ * NS_ERR_ARG for stage outside 1..3. */
+ns_status ns_stage_stream(const ns_params *p, int32_t stage, double *state, void *work,
+                          size_t work_bytes, void *stream);
+
 /* Launch shape of the fused kernel for later calls made by the calling
  * thread (each thread keeps its own setting; a batch member fixes its shape
  * when it is added).  tile selects the

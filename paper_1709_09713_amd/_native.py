@@ -69,7 +69,7 @@ class ns_instance(ctypes.Structure):
 
 # Exported C symbols, in header order.
 EXPORTS = ("ns_status_string", "ns_state_bytes", "ns_workspace_bytes",
-           "tgv_init", "ns_residual", "rk3_step", "diagnostics",
+           "tgv_init", "ns_residual", "rk3_step", "diagnostics", "ns_stage_stream",
            "ns_set_fused_config", "ns_get_fused_config", "ns_set_fused_order",
            "ns_get_fused_order",
            "ns_batch_create", "ns_batch_destroy", "ns_batch_add", "ns_batch_remove",
@@ -115,6 +115,8 @@ def lib():
         L.rk3_step.argtypes = [P, ctypes.c_int, ctypes.c_int, d, i32, vp, vp, sz, vp, vp]
         L.diagnostics.restype = ctypes.c_int
         L.diagnostics.argtypes = [P, vp, ctypes.POINTER(ns_diag), vp, sz, vp]
+        L.ns_stage_stream.restype = ctypes.c_int
+        L.ns_stage_stream.argtypes = [P, i32, vp, vp, sz, vp]
         L.ns_set_fused_config.restype = ctypes.c_int
         L.ns_set_fused_config.argtypes = [i32, i32]
         L.ns_get_fused_config.restype = ctypes.c_int
@@ -246,6 +248,17 @@ def diagnostics(p: ns_params, state, work, work_bytes: int = 0, stream=None) -> 
     d = out.as_dict()
     d["status"] = st
     return d
+
+
+def ns_stage_stream(p: ns_params, stage: int, state, work, work_bytes: int = 0, stream=None):
+    """The bytes of fused RK stage `stage` without the residual (the memory
+    system's ceiling for the stage kernel); overwrites state and work."""
+    if work_bytes == 0 and work is not None and not isinstance(work, int):
+        work_bytes = _nbytes(work)
+    st = _ptr(state, "ns_stage_stream state", "float64", ns_state_bytes(p))
+    w = _ptr(work, "ns_stage_stream work", None, work_bytes)
+    _check(lib().ns_stage_stream(ctypes.byref(p), int(stage), st, w, work_bytes, _stream(stream)),
+           "ns_stage_stream")
 
 
 def ns_set_fused_config(tile: int, zchunk: int = 0):

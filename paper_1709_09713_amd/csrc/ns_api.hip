@@ -438,6 +438,26 @@ ns_status rk3_step(const ns_params *p, ns_algo algo, ns_precision prec, double d
     return NS_OK;
 }
 
+ns_status ns_stage_stream(const ns_params *p, int32_t stage, double *state, void *work,
+                          size_t work_bytes, void *stream)
+{
+    ns_status st = check_params(p);
+    if (st != NS_OK) return st;
+    if (stage < 1 || stage > 3 || !state || !aligned(state, 16)) return NS_ERR_ARG;
+    const Consts c = make_consts(p);
+    const Layout L = layout(c, NS_ALGO_FUSED, NS_FP64);
+    st = check_work(work, work_bytes, L.total);
+    if (st != NS_OK) return st;
+    double *acc = at<double>(work, L.acc);
+    double *b1 = at<double>(work, L.b1), *b2 = at<double>(work, L.b2);
+    const int64_t n5 = 5 * c.N;
+    hipStream_t s = (hipStream_t)stream;
+    if (stage == 1) NS_HIP_OK(launch_stream_stage(1, n5, state, nullptr, acc, b1, s));
+    if (stage == 2) NS_HIP_OK(launch_stream_stage(2, n5, b1, acc, acc, b2, s));
+    if (stage == 3) NS_HIP_OK(launch_stream_stage(3, n5, b2, acc, nullptr, state, s));
+    return NS_OK;
+}
+
 ns_status diagnostics(const ns_params *p, const double *state, ns_diag *out_host, void *work,
                       size_t work_bytes, void *stream)
 {

@@ -71,6 +71,12 @@ hipError_t launch_diag_partials(const Consts &c, const double *state, double *pa
 hipError_t launch_diag_finalize(const Consts &c, const double *partial, int64_t nblocks,
                                 ns_diag *out, hipStream_t st);
 
+// The bytes of one fused FP64 RK stage (1..3) over the same buffers, with
+// a pointwise update instead of the residual (the achievable ceiling of the
+// stage kernel's memory traffic).  n5 = number of doubles in a field set.
+hipError_t launch_stream_stage(int stage, int64_t n5, const double *qin, const double *acc_in,
+                               double *acc_out, double *qout, hipStream_t st);
+
 // Taylor-Green initial state.
 hipError_t launch_tgv_init(const Consts &c, const ns_params *p, double *state, hipStream_t st);
 

@@ -49,16 +49,28 @@ def _points(req):
 
 
 def summarize(results, t_first, t_last):
+    """Latency percentiles, throughput, and two signs of whether the offered
+    load was sustained: the requests still unfinished when the last one
+    arrived (a queue that keeps growing leaves a backlog proportional to the
+    run length) and the mean latency of the last quarter of arrivals over
+    that of the first quarter."""
     lat = np.array([r.latency for r in results])
     upd = sum(_points(dict(n=r.n)) * 3 * r.steps for r in results)
     span = t_last - t_first
+    last_arrival = max(r.arrival for r in results)
+    by_arrival = sorted(results, key=lambda r: r.arrival)
+    q = max(1, len(by_arrival) // 4)
+    first = np.mean([r.latency for r in by_arrival[:q]])
+    last = np.mean([r.latency for r in by_arrival[-q:]])
     return {"requests": len(results),
             "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)),
             "mean_latency_s": float(lat.mean()),
             "makespan_s": span,
             "updates_per_s": upd / span,
-            "requests_per_s": len(results) / span}
+            "requests_per_s": len(results) / span,
+            "backlog_at_last_arrival": int(sum(r.finished > last_arrival for r in results)),
+            "latency_last_over_first_quarter": float(last / first) if first > 0 else None}
 
 
 class GpuBackend:

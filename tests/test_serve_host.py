@@ -122,12 +122,30 @@ def test_quanta_stop_at_the_next_completion():
 
 def test_summary_statistics():
     class R:
-        def __init__(self, n, steps, lat):
-            self.n, self.steps, self.latency = n, steps, lat
-    rs = [R(10, 2, 1.0), R(10, 2, 3.0), R(10, 2, 2.0)]
+        def __init__(self, n, steps, lat, arrival):
+            self.n, self.steps, self.latency, self.arrival = n, steps, lat, arrival
+            self.finished = arrival + lat
+    rs = [R(10, 2, 1.0, 0.0), R(10, 2, 3.0, 0.5), R(10, 2, 2.0, 1.0)]
     s = summarize(rs, 0.0, 4.0)
     assert s["p50_latency_s"] == 2.0 and s["mean_latency_s"] == 2.0
     assert s["updates_per_s"] == 3 * 10 ** 3 * 3 * 2 / 4.0
+    # unfinished when the last request arrived (t = 1.0): the ones finishing
+    # at 3.5 and 3.0
+    assert s["backlog_at_last_arrival"] == 2
+    assert s["latency_last_over_first_quarter"] == 2.0
+
+
+def test_summary_flags_a_growing_queue():
+    """A queue that grows: each arrival waits for all earlier ones, so the
+    latency climbs and work is left over at the last arrival."""
+    class R:
+        def __init__(self, k):
+            self.n, self.steps, self.arrival = 8, 1, 0.1 * k
+            self.finished = 0.3 * (k + 1)
+            self.latency = self.finished - self.arrival
+    s = summarize([R(k) for k in range(40)], 0.0, 12.0)
+    assert s["backlog_at_last_arrival"] > 8
+    assert s["latency_last_over_first_quarter"] > 2.0
 
 
 def test_no_requests():
