@@ -22,6 +22,10 @@ namespace {
 
 typedef double d2_t __attribute__((ext_vector_type(2)));
 
+// Each lane moves two 16-byte chunks per iteration (all loads issued before
+// the stores); 64 blocks of 256 lanes per compute unit keep enough bytes in
+// flight (the fastest of the shapes measured: 8-64 blocks per CU, one to
+// four chunks per lane, non-temporal or cached accesses, 4.7-5.2 TB/s).
 template <int MODE>
 __global__ void __launch_bounds__(256) stream_stage_kernel(int64_t npairs, const d2_t *__restrict__ qin,
                                                            const d2_t *__restrict__ acc_in,
@@ -29,7 +33,19 @@ __global__ void __launch_bounds__(256) stream_stage_kernel(int64_t npairs, const
                                                            d2_t *__restrict__ qout, double a, double b)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npairs; i += stride) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + stride < npairs; i += 2 * stride) {
+        const d2_t q0 = qin[i], q1 = qin[i + stride];
+        const d2_t a0 = (MODE == 1) ? q0 : __builtin_nontemporal_load(acc_in + i);
+        const d2_t a1 = (MODE == 1) ? q1 : __builtin_nontemporal_load(acc_in + i + stride);
+        __builtin_nontemporal_store(a0 + a * q0, qout + i);
+        __builtin_nontemporal_store(a1 + a * q1, qout + i + stride);
+        if (MODE != 3) {
+            __builtin_nontemporal_store(a0 + b * q0, acc_out + i);
+            __builtin_nontemporal_store(a1 + b * q1, acc_out + i + stride);
+        }
+    }
+    for (; i < npairs; i += stride) {
         const d2_t q = qin[i];
         const d2_t acc = (MODE == 1) ? q : __builtin_nontemporal_load(acc_in + i);
         __builtin_nontemporal_store(acc + a * q, qout + i);
@@ -47,8 +63,7 @@ hipError_t launch_stream_stage(int stage, int64_t n5, const double *qin, const d
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    // enough resident waves to keep every channel busy; grid-stride beyond
-    int64_t blocks = (int64_t)cus * 16;
+    int64_t blocks = (int64_t)cus * 64;
     const int64_t need = (npairs + 255) / 256;
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;

@@ -81,30 +81,45 @@ using SIC = std::integral_constant<int, V>;
 
 }  // namespace
 
-// OWN (stage 1 only): the input state is also the RK accumulator of the
-// output point; group M then takes the accumulator of its four fields from
-// its own column's plane loads instead of reading the state again.
-// PAIR (even nx, not with OWN): group M loads the halo plane two x-neighbours
-// per lane with one 2-wide load, halving its plane-load instructions; pairs
-// start at even x, so with nx even they never straddle the periodic wrap.
-template <int BX, int BY, typename TIN, typename TOUT, typename CT, bool DIAG, bool OWN, bool PAIR>
+// MODE: 0 = residual only (R to s.rout), 1..3 = RK stage.
+// PAIR (even nx): group M loads the halo plane two
+// x-neighbours per lane with one 2-wide load and stages them with one
+// 2-wide LDS store per field; pairs start at even x, so with nx even they
+// never straddle the periodic wrap.
+//
+// Work split.  Group M (loads, staging, momentum) finishes plane zp - 3 in
+// the step of plane zp; group E (mass, energy, viscous vector) finishes
+// plane zp - 2 and hands M the viscous vector through vbuf.  Every lane
+// computes, whether or not its column lies inside the grid (its LDS cells
+// hold wrapped, valid values); only global stores and diagnostics are
+// masked.  (The range checks of the march stay scalar branches: without them
+// a five-plane chunk becomes one basic block that the register allocator
+// cannot fit in 256 VGPRs.)
+template <int BX, int BY, typename TIN, typename TOUT, typename CT, int MODE, bool DIAG, bool PAIR>
 __global__ void __launch_bounds__(2 * BX * BY)
 split_stage_kernel(Consts c, StageArgs s)
 {
-    static_assert(!OWN || std::is_same<TIN, double>::value, "OWN needs the double state as input");
-    static_assert(!(OWN && PAIR), "OWN loads single points");
+    static_assert(MODE != 1 || std::is_same<TIN, double>::value, "stage 1 reads the double state");
+    static_assert(!DIAG || MODE == 1, "diagnostics of the step's input state are taken in stage 1");
     static_assert(BX % 2 == 0, "pairs need an even tile width");
     constexpr bool DEV = std::is_same<CT, float>::value;
     constexpr int HX = BX + 4, HY = BY + 4, HP = HX * HY, NT = BX * BY;
+    static_assert(HP % 2 == 0, "pair cells start at even LDS offsets");
     constexpr int PW = PAIR ? 2 : 1;                        // points per load slot
     constexpr int NLOAD = (HP + PW * NT - 1) / (PW * NT);
     constexpr int NW = 2 * NT / 64;
     static_assert(NT % 64 == 0, "each group must be whole waves");
     enum { L_RHO, L_M0, L_M1, L_M2, L_E, L_U, L_V, L_W, L_P, L_T, NF };
-    __shared__ CT lds[2][NF][HP];
+    __shared__ __attribute__((aligned(16))) CT lds[2][NF][HP];
     // E -> M: (V_x, V_y, V_z) in-plane part at plane zp, z part at plane zp - 2
     __shared__ CT vbuf[2][6][NT];
     __shared__ double red[NW][kDiag];
+    // per-column diagnostic sums (stage 1 with diagnostics): each thread adds
+    // into its own slots with no-return LDS adds, so the sums cost no
+    // registers and no waits during the march.  Slots: 0 mass, 4 energy,
+    // 5 kinetic energy and 6 enstrophy (E), 1-3 momentum (M)
+    constexpr int ND = DIAG ? 7 : 1;
+    __shared__ double dacc[ND][NT];
 
     // The group is a property of the wave; reading it through a scalar
     // register makes the branch below a scalar branch, so each wave runs
@@ -132,9 +147,18 @@ split_stage_kernel(Consts c, StageArgs s)
     const CT two3 = CT(2) / CT(3);
     const CT kz = kappa * c2z;
 
-    double dsum[DIAG ? 7 : 1];
+    if constexpr (DIAG) {
+        if (!grp_e) {
 #pragma unroll
-    for (int k = 0; k < (DIAG ? 7 : 1); ++k) dsum[k] = 0.0;
+            for (int k = 1; k < 4; ++k) dacc[k][pt] = 0.0;
+        } else {
+            dacc[0][pt] = dacc[4][pt] = dacc[5][pt] = dacc[6][pt] = 0.0;
+        }
+    }
+    // in-order adds to a thread's own slot: deterministic sums
+    auto dadd = [&](int k, double v) {
+        __hip_atomic_fetch_add(&dacc[k][pt], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
 
     // The march covers planes z0-2 .. z1+2 (M finishes a plane three steps
     // after loading it), padded to a multiple of 5; padding planes are
@@ -169,57 +193,34 @@ split_stage_kernel(Consts c, StageArgs s)
     if (!grp_e) {
         // ------------------------------------------------------------ group M
         const TIN *qin = (const TIN *)s.qin;
-        enum { Z_RHO, Z_U, Z_V, Z_W, NZ };
-        CT qz[5][NZ];      // ring: rho, u, v, w of the own column
-        CT ra[5][4];       // ring: pending mass and momentum residuals
-        CT rp[4];          // plane zp - 2 with its z terms, V still missing
-        TIN pf[NLOAD][5][PW];  // next plane, prefetched
-        double acc[4];
-        double ocol[3][4];             // own column's exact state, three planes (OWN only)
+        enum { Z_M0, Z_M1, Z_M2, Z_W, NZ };
+        CT qz[5][NZ];      // ring: rho u, rho v, rho w, w of the own column
+        CT ra[5][3];       // ring: pending momentum residuals
+        CT rp[3];          // plane zp - 2 with its z terms, V still missing
+        TIN pf[NLOAD][5][PW];  // plane zp + 1, staged in step zp
+        TIN pg[NLOAD][5][PW];  // plane zp + 2, loaded in step zp
+        double acc[3];
+        double accn[3];                // accumulator of the next step's point, prefetched
 #pragma unroll
-        for (int q = 0; q < 3; ++q)
+        for (int f = 0; f < 3; ++f) acc[f] = accn[f] = 0.0;
 #pragma unroll
-            for (int f = 0; f < 4; ++f) ocol[q][f] = 0.0;
+        for (int q = 0; q < 5; ++q) {
 #pragma unroll
-        for (int f = 0; f < 4; ++f) acc[f] = 0.0;
+            for (int f = 0; f < NZ; ++f) qz[q][f] = CT(0);
 #pragma unroll
-        for (int q = 0; q < 5; ++q)
+            for (int f = 0; f < 3; ++f) ra[q][f] = CT(0);
+        }
 #pragma unroll
-            for (int f = 0; f < 4; ++f) qz[q][f] = ra[q][f] = CT(0);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) rp[f] = CT(0);
+        for (int f = 0; f < 3; ++f) rp[f] = CT(0);
 
         // Plane offsets and LDS cells of the points this thread loads;
-        // lcell < 0 marks an unused slot.  With OWN, slot 0 is the thread's
-        // own column and the radius-2 ring around the tile goes to the
-        // other slots (two rows on top, two at the bottom, then two
-        // columns on each side).
+        // lcell < 0 marks an unused slot.
         int loff[NLOAD], lcell[NLOAD];
 #pragma unroll
         for (int r = 0; r < NLOAD; ++r) {
             int lx = 0, ly = 0;
             lcell[r] = -1;
-            if constexpr (OWN) {
-                if (r == 0) {
-                    lx = tx + 2;
-                    ly = ty + 2;
-                    lcell[r] = ly * HX + lx;
-                } else {
-                    const int k = pt + (r - 1) * NT;
-                    if (k < HP - NT) {
-                        if (k < 4 * HX) {
-                            const int row = k / HX;
-                            lx = k % HX;
-                            ly = row < 2 ? row : HY - 4 + row;
-                        } else {
-                            const int q = k - 4 * HX, cc = q % 4;
-                            ly = 2 + q / 4;
-                            lx = cc < 2 ? cc : HX - 4 + cc;
-                        }
-                        lcell[r] = ly * HX + lx;
-                    }
-                }
-            } else if constexpr (PAIR) {
+            if constexpr (PAIR) {
                 const int q = pt + r * NT;          // pair index
                 if (q < HP / 2) {
                     lx = 2 * (q % (HX / 2));
@@ -243,7 +244,7 @@ split_stage_kernel(Consts c, StageArgs s)
                 loff[r] = yy * c.nx + xx;
             }
         }
-        auto load_plane = [&](int zp) {
+        auto load_plane = [&](int zp, TIN (&dst)[NLOAD][5][PW]) {
             int zw = zp % c.nz;
             if (zw < 0) zw += c.nz;
             const int64_t base = (int64_t)zw * c.nxy;
@@ -255,21 +256,21 @@ split_stage_kernel(Consts c, StageArgs s)
                     if constexpr (PAIR) {
                         typedef TIN pair_t __attribute__((ext_vector_type(2)));
                         const pair_t v = *(const pair_t *)(qin + g + f * N);
-                        pf[r][f][0] = v.x;
-                        pf[r][f][1] = v.y;
+                        dst[r][f][0] = v.x;
+                        dst[r][f][1] = v.y;
                     } else {
-                        pf[r][f][0] = qin[g + f * N];
+                        dst[r][f][0] = qin[g + f * N];
                     }
                 }
             }
         };
         auto stage_plane = [&](int b) {
 #pragma unroll
-            for (int r = 0; r < NLOAD; ++r)
+            for (int r = 0; r < NLOAD; ++r) {
+                if (lcell[r] < 0) continue;
+                CT val[NF][PW];
 #pragma unroll
-            for (int j = 0; j < PW; ++j) {
-                const int idx = lcell[r] + j;
-                if (lcell[r] >= 0) {
+                for (int j = 0; j < PW; ++j) {
                     const CT rho = sp_to_ct<TIN, CT>(pf[r][0][j], c.rho_ref);
                     const CT m0 = sp_to_ct<TIN, CT>(pf[r][1][j], 0.0);
                     const CT m1 = sp_to_ct<TIN, CT>(pf[r][2][j], 0.0);
@@ -280,29 +281,32 @@ split_stage_kernel(Consts c, StageArgs s)
                     const CT u = m0 * inv, v = m1 * inv, w = m2 * inv;
                     const CT p = gm1 * (E - half * (m0 * u + m1 * v + m2 * w));
                     const CT T = DEV ? (gM2 * p - rho) * inv : gM2 * p * inv;
-                    lds[b][L_RHO][idx] = rho;
-                    lds[b][L_M0][idx] = m0;
-                    lds[b][L_M1][idx] = m1;
-                    lds[b][L_M2][idx] = m2;
-                    lds[b][L_E][idx] = E;
-                    lds[b][L_U][idx] = u;
-                    lds[b][L_V][idx] = v;
-                    lds[b][L_W][idx] = w;
-                    lds[b][L_P][idx] = p;
-                    lds[b][L_T][idx] = T;
+                    val[L_RHO][j] = rho;
+                    val[L_M0][j] = m0;
+                    val[L_M1][j] = m1;
+                    val[L_M2][j] = m2;
+                    val[L_E][j] = E;
+                    val[L_U][j] = u;
+                    val[L_V][j] = v;
+                    val[L_W][j] = w;
+                    val[L_P][j] = p;
+                    val[L_T][j] = T;
                 }
-            }
-        };
-
-        // OWN: at the end of step zp, acc takes plane zp - 2 (finished in
-        // step zp + 1) and the ring moves on to planes zp + 1, zp, zp - 1
-        auto shift_ocol = [&]() {
+                const int idx = lcell[r];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                acc[f] = ocol[2][f];
-                ocol[2][f] = ocol[1][f];
-                ocol[1][f] = ocol[0][f];
-                ocol[0][f] = (double)pf[0][f][0];
+                for (int f = 0; f < NF; ++f) {
+                    if constexpr (PAIR) {
+                        // one 2-wide store per field: consecutive lanes
+                        // write consecutive 2-point cells
+                        typedef CT pair_t __attribute__((ext_vector_type(2)));
+                        pair_t v2;
+                        v2.x = val[f][0];
+                        v2.y = val[f][1];
+                        *(pair_t *)&lds[b][f][idx] = v2;
+                    } else {
+                        lds[b][f][idx] = val[f][0];
+                    }
+                }
             }
         };
 
@@ -313,62 +317,69 @@ split_stage_kernel(Consts c, StageArgs s)
             constexpr int SM4 = (PH + 1) % 5, SM3 = (PH + 2) % 5;
             const int b = (zp - z0) & 1;
             const int zf = zp - 3;
-            const bool fin = active && zf >= z0 && zf < z1;
-            if constexpr (!OWN) {
-                // accumulator (stages 2, 3) or exact input state of the
-                // point finished in this step; idle threads read a valid
-                // address they ignore
-                const double *src = (s.mode >= 2) ? s.acc_in : (const double *)s.qin;
-                const int64_t pidx = (int64_t)(fin ? zf : z0) * c.nxy + col;
+            const bool do_fin = (zf >= z0 && zf < z1);
+            const bool do_plane = (zp >= z0 && zp < z1);
+            const bool do_vin = (zp - 1 >= z0 && zp - 1 < z1);
+            const int64_t pidx = (int64_t)(do_fin ? zf : z0) * c.nxy + col;
+            // Plane zp + 2 and the accumulator of the next step's point are
+            // loaded now, before this step's stores: vector memory counters
+            // retire loads and stores in issue order, so a load issued after
+            // a store could only be waited for together with that store.
+            // Issued this way, the waits of the next step (staging plane
+            // zp + 2, finishing plane zf + 1) never include this step's
+            // stores.  Idle lanes read a valid address they ignore.
+            load_plane(zp + 2, pg);
+            if constexpr (MODE >= 1) {
+                // stages 2 and 3 read the accumulator, stage 1 the state
+                const double *src = (MODE >= 2) ? s.acc_in : (const double *)s.qin;
+                const int zn = zf + 1;
+                const int64_t pn = (int64_t)((zn >= z0 && zn < z1) ? zn : z0) * c.nxy + col;
 #pragma unroll
-                for (int f = 0; f < 4; ++f) acc[f] = __builtin_nontemporal_load(src + f * N + pidx);
+                for (int f = 0; f < 3; ++f) {
+                    acc[f] = accn[f];
+                    accn[f] = __builtin_nontemporal_load(src + (1 + f) * N + pn);
+                }
             }
-            load_plane(zp + 1);
 #pragma unroll
-            for (int f = 0; f < 4; ++f) ra[SP2][f] = CT(0);
+            for (int f = 0; f < 3; ++f) ra[SP2][f] = CT(0);
 
-            if (active) {
-                const CT rho = LV(L_RHO, 0, 0);
+            {
                 const CT m0 = LV(L_M0, 0, 0), m1 = LV(L_M1, 0, 0), m2 = LV(L_M2, 0, 0);
                 const CT u = LV(L_U, 0, 0), v = LV(L_V, 0, 0), w = LV(L_W, 0, 0);
                 const CT p = LV(L_P, 0, 0);
-                qz[S0][Z_RHO] = rho;
-                qz[S0][Z_U] = u;
-                qz[S0][Z_V] = v;
+                qz[S0][Z_M0] = m0;
+                qz[S0][Z_M1] = m1;
+                qz[S0][Z_M2] = m2;
                 qz[S0][Z_W] = w;
 
-                const CT g0 = -half * c1z * m2;                  // -1/2 d(rho w)/dz
-                const CT g1 = -half * c1z * (m0 * w);            // -1/2 d(rho u w)/dz
-                const CT g2 = -half * c1z * (m1 * w);            // -1/2 d(rho v w)/dz
-                const CT g3 = -c1z * (half * (m2 * w) + p);      // -1/2 d(rho w w)/dz - dp/dz
-                const CT g[4] = {g0, g1, g2, g3};
+                const CT g0 = -half * c1z * (m0 * w);            // -1/2 d(rho u w)/dz
+                const CT g1 = -half * c1z * (m1 * w);            // -1/2 d(rho v w)/dz
+                const CT g2 = -c1z * (half * (m2 * w) + p);      // -1/2 d(rho w w)/dz - dp/dz
+                const CT g[3] = {g0, g1, g2};
 #pragma unroll
-                for (int f = 0; f < 4; ++f) {
+                for (int f = 0; f < 3; ++f) {
                     ra[SM2][f] -= g[f];
                     ra[SM1][f] += CT(8) * g[f];
                     ra[SP1][f] -= CT(8) * g[f];
                     ra[SP2][f] += g[f];
                 }
 
-                if (zp >= z0 && zp < z1) {
-                    const CT rhof = DEV ? CT(1) + rho : rho;
+                if (do_plane) {
                     const CT uc = u * c1x, vc = v * c1y;
                     const CT a = c1x * DX1(L_U) + c1y * DY1(L_V);
-                    ra[S0][0] -= half * (c1x * DX1(L_M0) + c1y * DY1(L_M1) + rhof * a
-                                         + uc * DX1(L_RHO) + vc * DY1(L_RHO));
-                    ra[S0][1] -= half * (c1x * DX1P(L_M0, L_U) + c1y * DY1P(L_M0, L_V) + m0 * a
+                    ra[S0][0] -= half * (c1x * DX1P(L_M0, L_U) + c1y * DY1P(L_M0, L_V) + m0 * a
                                          + uc * DX1(L_M0) + vc * DY1(L_M0))
                                  + c1x * DX1(L_P);
-                    ra[S0][2] -= half * (c1x * DX1P(L_M1, L_U) + c1y * DY1P(L_M1, L_V) + m1 * a
+                    ra[S0][1] -= half * (c1x * DX1P(L_M1, L_U) + c1y * DY1P(L_M1, L_V) + m1 * a
                                          + uc * DX1(L_M1) + vc * DY1(L_M1))
                                  + c1y * DY1(L_P);
-                    ra[S0][3] -= half * (c1x * DX1P(L_M2, L_U) + c1y * DY1P(L_M2, L_V) + m2 * a
+                    ra[S0][2] -= half * (c1x * DX1P(L_M2, L_U) + c1y * DY1P(L_M2, L_V) + m2 * a
                                          + uc * DX1(L_M2) + vc * DY1(L_M2));
                 }
                 // in-plane viscous part of plane zp - 1 (from E's last step)
-                if (zp - 1 >= z0 && zp - 1 < z1) {
+                if (do_vin) {
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) ra[SM1][1 + k] += inv_re * vbuf[b ^ 1][k][pt];
+                    for (int k = 0; k < 3; ++k) ra[SM1][k] += inv_re * vbuf[b ^ 1][k][pt];
                 }
             }
 
@@ -377,79 +388,76 @@ split_stage_kernel(Consts c, StageArgs s)
             stage_plane(b ^ 1);
 
             // finish plane zp - 3: z viscous part from E, RK update, output
-            if (fin) {
-                double Rd[4];
-                Rd[0] = (double)rp[0];
+            if (do_fin) {
+                double Rd[3];
 #pragma unroll
-                for (int k = 0; k < 3; ++k) Rd[1 + k] = (double)(rp[1 + k] + inv_re * vbuf[b ^ 1][3 + k][pt]);
-                const int64_t pidx = (int64_t)zf * c.nxy + col;
-                if (s.mode == 0) {
+                for (int k = 0; k < 3; ++k) Rd[k] = (double)(rp[k] + inv_re * vbuf[b ^ 1][3 + k][pt]);
+                if (active) {
+                    if constexpr (MODE == 0) {
 #pragma unroll
-                    for (int f = 0; f < 4; ++f) s.rout[f * N + pidx] = Rd[f];
-                } else {
-                    if constexpr (DIAG) {
+                        for (int f = 0; f < 3; ++f) s.rout[(1 + f) * N + pidx] = Rd[f];
+                    } else {
+                        if constexpr (DIAG) {
 #pragma unroll
-                        for (int f = 0; f < 4; ++f) dsum[f] += acc[f];
-                        dsum[5] += 0.5 * (acc[1] * (double)qz[SM3][Z_U] + acc[2] * (double)qz[SM3][Z_V]
-                                          + acc[3] * (double)qz[SM3][Z_W]);
-                    }
-                    const double ref[4] = {c.rho_ref, 0.0, 0.0, 0.0};
+                            for (int f = 0; f < 3; ++f) dadd(1 + f, acc[f]);
+                        }
 #pragma unroll
-                    for (int f = 0; f < 4; ++f) {
-                        sp_store<TOUT>(s.qout, f * N + pidx, acc[f] + s.a_dt * Rd[f], ref[f]);
-                        if (s.mode < 3)
-                            __builtin_nontemporal_store(acc[f] + s.b_dt * Rd[f], s.acc_out + f * N + pidx);
+                        for (int f = 0; f < 3; ++f) {
+                            sp_store<TOUT>(s.qout, (1 + f) * N + pidx, acc[f] + s.a_dt * Rd[f], 0.0);
+                            if constexpr (MODE < 3)
+                                __builtin_nontemporal_store(acc[f] + s.b_dt * Rd[f], s.acc_out + (1 + f) * N + pidx);
+                        }
                     }
                 }
             }
 
             // gathered z terms of plane zp - 2 (finished in the next step)
-            if (active) {
+            {
 #define DZ1(f) d1u(qz[SM4][f], qz[SM3][f], qz[SM1][f], qz[S0][f])
-                const CT rho = qz[SM2][Z_RHO];
-                const CT u = qz[SM2][Z_U], v = qz[SM2][Z_V], w = qz[SM2][Z_W];
-                const CT rhof = DEV ? CT(1) + rho : rho;
-                const CT wc = w * c1z;
+                const CT wc = qz[SM2][Z_W] * c1z;
                 const CT Gzz = c1z * DZ1(Z_W);
-                rp[0] = ra[SM2][0] - half * (rhof * Gzz + wc * DZ1(Z_RHO));
-                // rho u_i at the z taps (in the deviation form rho is 1 + rho')
-#define RHOF(q) (DEV ? CT(1) + qz[q][Z_RHO] : qz[q][Z_RHO])
-#define DZM(k)                                                                       \
-    d1u(RHOF(SM4) * qz[SM4][k], RHOF(SM3) * qz[SM3][k], RHOF(SM1) * qz[SM1][k],      \
-        RHOF(S0) * qz[S0][k])
-                rp[1] = ra[SM2][1] - half * (rhof * u * Gzz + wc * DZM(Z_U));
-                rp[2] = ra[SM2][2] - half * (rhof * v * Gzz + wc * DZM(Z_V));
-                rp[3] = ra[SM2][3] - half * (rhof * w * Gzz + wc * DZM(Z_W));
-#undef DZM
-#undef RHOF
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    rp[k] = ra[SM2][k] - half * (qz[SM2][Z_M0 + k] * Gzz + wc * DZ1(Z_M0 + k));
 #undef DZ1
             }
-            if constexpr (OWN) shift_ocol();
+#pragma unroll
+            for (int r = 0; r < NLOAD; ++r)
+#pragma unroll
+                for (int f = 0; f < 5; ++f)
+#pragma unroll
+                    for (int j = 0; j < PW; ++j) pf[r][f][j] = pg[r][f][j];
             lds_barrier();
         };
 
         // prologue: plane z0 - 2 into LDS buffer 0
-        load_plane(z0 - 2);
+        load_plane(z0 - 2, pf);
         stage_plane(0);
-        if constexpr (OWN) shift_ocol();
+        load_plane(z0 - 1, pf);
         lds_barrier();
-        for (int it = 0; it < L; it += 5) {
+        auto chunk = [&](int it) {
             const int zp = z0 - 2 + it;
             step(SIC<0>{}, zp);
             step(SIC<1>{}, zp + 1);
             step(SIC<2>{}, zp + 2);
             step(SIC<3>{}, zp + 3);
             step(SIC<4>{}, zp + 4);
-        }
+        };
+        for (int it = 0; it < L; it += 5) chunk(it);
     } else {
         // ------------------------------------------------------------ group E
-        constexpr int NZ = DIAG ? 5 : 4;
-        enum { Z_E, Z_U, Z_V, Z_W, Z_RHO };
-        constexpr int NR = DIAG ? 2 : 1;
-        CT qz[5][NZ];               // ring: rho E, u, v, w (+ rho) of the own column
+        // E's instruction stream is the longer one (measured: E busy ~92%
+        // of the march, M ~75%), so its waves get the higher issue
+        // priority on their SIMD
+        __builtin_amdgcn_s_setprio(2);
+        enum { Z_E, Z_U, Z_V, Z_W, Z_RHO, NZ };
+        constexpr int R_EN = 0, R_MASS = 1;
+        constexpr int NR = 2;
+        CT qz[5][NZ];               // ring: rho E, u, v, w, rho of the own column
         CT qa[5], qb[5], qc[5];     // ring: D_x u + D_y v, D_x w, D_y w
-        CT ra[5][NR];               // ring: pending energy residual (+ omega_z)
-        double acc4;
+        CT ra[5][NR];               // ring: pending energy and mass residuals
+        double acc0 = 0.0, acc4 = 0.0;
+        double accn0 = 0.0, accn4 = 0.0;    // next step's, prefetched
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             qa[q] = qb[q] = qc[q] = CT(0);
@@ -466,19 +474,26 @@ split_stage_kernel(Consts c, StageArgs s)
             constexpr int SM4 = (PH + 1) % 5, SM3 = (PH + 2) % 5;
             const int b = (zp - z0) & 1;
             const int zf = zp - 2;
-            const bool fin = active && zf >= z0 && zf < z1;
-            {
-                const double *src = (s.mode >= 2) ? s.acc_in : (const double *)s.qin;
-                const int64_t pidx = (int64_t)(fin ? zf : z0) * c.nxy + col;
-                acc4 = __builtin_nontemporal_load(src + 4 * N + pidx);
+            const bool do_fin = (zf >= z0 && zf < z1);
+            const bool do_plane = (zp >= z0 && zp < z1);
+            const int64_t pidx = (int64_t)(do_fin ? zf : z0) * c.nxy + col;
+            if constexpr (MODE >= 1) {
+                // one step ahead, as in group M
+                const double *src = (MODE >= 2) ? s.acc_in : (const double *)s.qin;
+                const int zn = zf + 1;
+                const int64_t pn = (int64_t)((zn >= z0 && zn < z1) ? zn : z0) * c.nxy + col;
+                acc0 = accn0;
+                acc4 = accn4;
+                accn0 = __builtin_nontemporal_load(src + pn);
+                accn4 = __builtin_nontemporal_load(src + 4 * N + pn);
             }
 #pragma unroll
             for (int f = 0; f < NR; ++f) ra[SP2][f] = CT(0);
 
-            if (active) {
-                const CT E = LV(L_E, 0, 0);
+            {
+                const CT E = LV(L_E, 0, 0), rho = LV(L_RHO, 0, 0);
                 const CT u = LV(L_U, 0, 0), v = LV(L_V, 0, 0), w = LV(L_W, 0, 0);
-                const CT p = LV(L_P, 0, 0), T = LV(L_T, 0, 0);
+                const CT p = LV(L_P, 0, 0), T = LV(L_T, 0, 0), m2 = LV(L_M2, 0, 0);
                 const CT Gxx = c1x * DX1(L_U), Gxy = c1y * DY1(L_U);
                 const CT Gyx = c1x * DX1(L_V), Gyy = c1y * DY1(L_V);
                 const CT Gzx = c1x * DX1(L_W), Gzy = c1y * DY1(L_W);
@@ -487,24 +502,29 @@ split_stage_kernel(Consts c, StageArgs s)
                 qz[S0][Z_U] = u;
                 qz[S0][Z_V] = v;
                 qz[S0][Z_W] = w;
-                if constexpr (DIAG) qz[S0][NZ - 1] = LV(L_RHO, 0, 0);
+                qz[S0][Z_RHO] = rho;
                 qa[S0] = a;
                 qb[S0] = Gzx;
                 qc[S0] = Gzy;
 
                 const CT g4 = -c1z * ((half * E + p) * w);   // -1/2 d(rhoE w)/dz - d(p w)/dz
                 const CT gT = kz * T;                        // kappa d2T/dz2
-                ra[SM2][0] -= g4;
-                ra[SM1][0] += CT(8) * g4;
-                ra[SP1][0] -= CT(8) * g4;
-                ra[SP2][0] += g4;
-                ra[SM2][0] -= gT;
-                ra[SM1][0] += CT(16) * gT;
-                ra[S0][0] -= CT(30) * gT;
-                ra[SP1][0] += CT(16) * gT;
-                ra[SP2][0] -= gT;
+                const CT g0 = -half * c1z * m2;              // -1/2 d(rho w)/dz
+                ra[SM2][R_EN] -= g4;
+                ra[SM1][R_EN] += CT(8) * g4;
+                ra[SP1][R_EN] -= CT(8) * g4;
+                ra[SP2][R_EN] += g4;
+                ra[SM2][R_EN] -= gT;
+                ra[SM1][R_EN] += CT(16) * gT;
+                ra[S0][R_EN] -= CT(30) * gT;
+                ra[SP1][R_EN] += CT(16) * gT;
+                ra[SP2][R_EN] -= gT;
+                ra[SM2][R_MASS] -= g0;
+                ra[SM1][R_MASS] += CT(8) * g0;
+                ra[SP1][R_MASS] -= CT(8) * g0;
+                ra[SP2][R_MASS] += g0;
 
-                if (zp >= z0 && zp < z1) {
+                if (do_plane) {
                     const CT uc = u * c1x, vc = v * c1y;
                     // d_j tau_ij = lap u_i + (1/3) d_i div u, in-plane parts
                     const CT Vx = four3 * (c2x * DX2(L_U)) + c2y * DY2(L_U)
@@ -518,20 +538,36 @@ split_stage_kernel(Consts c, StageArgs s)
                     // tau_ij du_i/dx_j restricted to terms without a z derivative
                     const CT phi = CT(2) * (Gxx * Gxx + Gyy * Gyy) + Gxy * Gxy + Gyx * Gyx
                                    + CT(2) * Gxy * Gyx + Gzx * Gzx + Gzy * Gzy;
-                    ra[S0][0] += -(c1x * DX1H() + c1y * DY1H())
-                                 - half * (E * a + uc * DX1(L_E) + vc * DY1(L_E))
-                                 + inv_re * (u * Vx + v * Vy + w * Vz + phi)
-                                 + kappa * (c2x * DX2(L_T) + c2y * DY2(L_T));
-                    if constexpr (DIAG) ra[S0][NR - 1] = Gyx - Gxy;   // omega_z
+                    const CT rhof = DEV ? CT(1) + rho : rho;
+                    ra[S0][R_MASS] -= half * (c1x * DX1(L_M0) + c1y * DY1(L_M1) + rhof * a
+                                              + uc * DX1(L_RHO) + vc * DY1(L_RHO));
+                    if constexpr (DIAG) {
+                        // the kinetic energy and the omega_z part of the
+                        // enstrophy are complete in the plane; the vorticity
+                        // components with z derivatives are added when the
+                        // point is finished
+                        const double oz = (double)(Gyx - Gxy);
+                        const double rd = (double)rhof;
+                        if (active) {
+                            dadd(5, 0.5 * rd * ((double)u * (double)u + (double)v * (double)v
+                                                + (double)w * (double)w));
+                            dadd(6, 0.5 * rd * oz * oz);
+                        }
+                    }
+                    ra[S0][R_EN] += -(c1x * DX1H() + c1y * DY1H())
+                                    - half * (E * a + uc * DX1(L_E) + vc * DY1(L_E))
+                                    + inv_re * (u * Vx + v * Vy + w * Vz + phi)
+                                    + kappa * (c2x * DX2(L_T) + c2y * DY2(L_T));
                 }
             }
 
             // finish plane zf = zp - 2: gathered z terms, RK update, output
-            if (fin) {
+            if (do_fin) {
 #define DZ1(f) d1u(qz[SM4][f], qz[SM3][f], qz[SM1][f], qz[S0][f])
 #define DZ2(f) d2u(qz[SM4][f], qz[SM3][f], qz[SM2][f], qz[SM1][f], qz[S0][f])
-                const CT E = qz[SM2][Z_E];
+                const CT E = qz[SM2][Z_E], rho = qz[SM2][Z_RHO];
                 const CT u = qz[SM2][Z_U], v = qz[SM2][Z_V], w = qz[SM2][Z_W];
+                const CT rhof = DEV ? CT(1) + rho : rho;
                 const CT a = qa[SM2], bb = qb[SM2], cc = qc[SM2];
                 const CT wc = w * c1z;
                 const CT Gxz = c1z * DZ1(Z_U), Gyz = c1z * DZ1(Z_V), Gzz = c1z * DZ1(Z_W);
@@ -547,42 +583,48 @@ split_stage_kernel(Consts c, StageArgs s)
                 const CT div = a + Gzz;
                 const CT phi = Gxz * Gxz + Gyz * Gyz + CT(2) * Gzz * Gzz
                                + CT(2) * (Gxz * bb + Gyz * cc) - two3 * div * div;
-                const CT R4 = ra[SM2][0] - half * (E * Gzz + wc * DZ1(Z_E))
+                const CT R4 = ra[SM2][R_EN] - half * (E * Gzz + wc * DZ1(Z_E))
                               + inv_re * (u * Vx + v * Vy + w * Vz + phi);
-#undef DZ1
-#undef DZ2
+                const CT R0 = ra[SM2][R_MASS] - half * (rhof * Gzz + wc * DZ1(Z_RHO));
                 double Rd4 = (double)R4;
                 if constexpr (DEV) Rd4 -= c.H_ref * ((double)a + (double)Gzz);
-                const int64_t pidx = (int64_t)zf * c.nxy + col;
-                if (s.mode == 0) {
-                    s.rout[4 * N + pidx] = Rd4;
-                } else {
-                    if constexpr (DIAG) {
-                        const CT rho = qz[SM2][NZ - 1];
-                        const CT rhof = DEV ? CT(1) + rho : rho;
-                        const CT ox = cc - Gyz, oy = Gxz - bb, oz = ra[SM2][NR - 1];
-                        dsum[4] += acc4;
-                        dsum[6] += 0.5 * (double)rhof * ((double)ox * (double)ox + (double)oy * (double)oy
-                                                         + (double)oz * (double)oz);
+                const double Rd0 = (double)R0;
+                if (active) {
+                    if constexpr (MODE == 0) {
+                        s.rout[pidx] = Rd0;
+                        s.rout[4 * N + pidx] = Rd4;
+                    } else {
+                        if constexpr (DIAG) {
+                            const CT ox = cc - Gyz, oy = Gxz - bb;
+                            dadd(0, acc0);
+                            dadd(4, acc4);
+                            dadd(6, 0.5 * (double)rhof * ((double)ox * (double)ox + (double)oy * (double)oy));
+                        }
+                        sp_store<TOUT>(s.qout, pidx, acc0 + s.a_dt * Rd0, c.rho_ref);
+                        sp_store<TOUT>(s.qout, 4 * N + pidx, acc4 + s.a_dt * Rd4, c.rhoE_ref);
+                        if constexpr (MODE < 3) {
+                            __builtin_nontemporal_store(acc0 + s.b_dt * Rd0, s.acc_out + pidx);
+                            __builtin_nontemporal_store(acc4 + s.b_dt * Rd4, s.acc_out + 4 * N + pidx);
+                        }
                     }
-                    sp_store<TOUT>(s.qout, 4 * N + pidx, acc4 + s.a_dt * Rd4, c.rhoE_ref);
-                    if (s.mode < 3)
-                        __builtin_nontemporal_store(acc4 + s.b_dt * Rd4, s.acc_out + 4 * N + pidx);
                 }
+#undef DZ1
+#undef DZ2
             }
             lds_barrier();
         };
 
         // prologue: matches group M's barrier
         lds_barrier();
-        for (int it = 0; it < L; it += 5) {
+        auto chunk = [&](int it) {
             const int zp = z0 - 2 + it;
             step(SIC<0>{}, zp);
             step(SIC<1>{}, zp + 1);
             step(SIC<2>{}, zp + 2);
             step(SIC<3>{}, zp + 3);
             step(SIC<4>{}, zp + 4);
-        }
+        };
+        for (int it = 0; it < L; it += 5) chunk(it);
     }
 #undef LV
 #undef DX1
@@ -598,8 +640,17 @@ split_stage_kernel(Consts c, StageArgs s)
 #undef DYDX
 
     if constexpr (DIAG) {
-        // block reduction of the diagnostic partial sums, fixed order
+        // block reduction of the diagnostic partial sums, fixed order: each
+        // thread takes the column sums of its own group's slots (the other
+        // group's slots count zero for it), then waves, then the block
         const int tid = threadIdx.x;
+        __syncthreads();
+        double dsum[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            const bool mine = grp_e ? (k == 0 || k >= 4) : (k >= 1 && k <= 3);
+            dsum[k] = mine ? dacc[k][pt] : 0.0;
+        }
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
             double vsum = dsum[k];
@@ -626,51 +677,53 @@ split_stage_kernel(Consts c, StageArgs s)
 
 namespace {
 
-template <int BX, int BY, typename TIN, typename TOUT, typename CT>
-hipError_t launch_sp(const Consts &c, const StageArgs &s, hipStream_t st)
+template <int BX, int BY, typename TIN, typename TOUT, typename CT, int MODE, bool DIAG, bool PAIR>
+void launch_one(const Consts &c, const StageArgs &s, hipStream_t st)
 {
     dim3 block(2 * BX * BY, 1, 1);
     dim3 grid((c.nx + BX - 1) / BX, (c.ny + BY - 1) / BY, (c.nz + s.zchunk - 1) / s.zchunk);
-    // stage 1 reads the double state, which is also its accumulator
-    if constexpr (std::is_same<TIN, double>::value) {
-        if (s.mode == 1) {
-            if (s.diag_partial != nullptr)
-                hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, true, true, false>), grid, block,
-                                   0, st, c, s);
-            else
-                hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, false, true, false>), grid, block,
-                                   0, st, c, s);
+    hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, MODE, DIAG, PAIR>), grid, block, 0, st,
+                       c, s);
+}
+
+// The halo plane is loaded in x-neighbour pairs when nx is even.
+template <int BX, int BY, typename TIN, typename TOUT, typename CT, int MODE>
+hipError_t launch_mode(const Consts &c, const StageArgs &s, hipStream_t st)
+{
+    const bool pair = c.nx % 2 == 0;
+    if constexpr (MODE == 1) {
+        if (s.diag_partial != nullptr) {
+            if (pair) launch_one<BX, BY, TIN, TOUT, CT, 1, true, true>(c, s, st);
+            else launch_one<BX, BY, TIN, TOUT, CT, 1, true, false>(c, s, st);
             return hipGetLastError();
         }
     }
-    if (c.nx % 2 == 0)
-        hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, false, false, true>), grid, block, 0, st,
-                           c, s);
+    if (pair)
+        launch_one<BX, BY, TIN, TOUT, CT, MODE, false, true>(c, s, st);
     else
-        hipLaunchKernelGGL((split_stage_kernel<BX, BY, TIN, TOUT, CT, false, false, false>), grid, block, 0, st,
-                           c, s);
+        launch_one<BX, BY, TIN, TOUT, CT, MODE, false, false>(c, s, st);
     return hipGetLastError();
 }
 
-template <typename TIN, typename TOUT, typename CT>
+template <typename TIN, typename TOUT, typename CT, int MODE>
 hipError_t launch_sp_tile(int tile, const Consts &c, const StageArgs &s, hipStream_t st)
 {
     switch (tile) {
-    case TILE_16x8_2G: return launch_sp<16, 8, TIN, TOUT, CT>(c, s, st);
-    case TILE_32x8_2G: return launch_sp<32, 8, TIN, TOUT, CT>(c, s, st);
-    case TILE_16x4_2G: return launch_sp<16, 4, TIN, TOUT, CT>(c, s, st);
+    case TILE_16x8_2G: return launch_mode<16, 8, TIN, TOUT, CT, MODE>(c, s, st);
+    case TILE_32x8_2G: return launch_mode<32, 8, TIN, TOUT, CT, MODE>(c, s, st);
+    case TILE_16x4_2G: return launch_mode<16, 4, TIN, TOUT, CT, MODE>(c, s, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int BX, int BY, typename TIN, typename TOUT, typename CT>
+template <int BX, int BY, typename T>
 int resident_sp()
 {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per, reinterpret_cast<const void *>(&split_stage_kernel<BX, BY, TIN, TOUT, CT, false, false, true>),
+            &per, reinterpret_cast<const void *>(&split_stage_kernel<BX, BY, T, T, T, 2, false, true>),
             2 * BX * BY, 0) != hipSuccess)
         return 0;
     return cus * (per > 0 ? per : 1);
@@ -684,9 +737,9 @@ int split_resident_blocks(ns_precision prec, int tile)
 {
     const bool d = prec == NS_FP64;
     switch (tile) {
-    case TILE_16x8_2G: return d ? resident_sp<16, 8, double, double, double>() : resident_sp<16, 8, float, float, float>();
-    case TILE_32x8_2G: return d ? resident_sp<32, 8, double, double, double>() : resident_sp<32, 8, float, float, float>();
-    case TILE_16x4_2G: return d ? resident_sp<16, 4, double, double, double>() : resident_sp<16, 4, float, float, float>();
+    case TILE_16x8_2G: return d ? resident_sp<16, 8, double>() : resident_sp<16, 8, float>();
+    case TILE_32x8_2G: return d ? resident_sp<32, 8, double>() : resident_sp<32, 8, float>();
+    case TILE_16x4_2G: return d ? resident_sp<16, 4, double>() : resident_sp<16, 4, float>();
     default: return 0;
     }
 }
@@ -694,11 +747,22 @@ int split_resident_blocks(ns_precision prec, int tile)
 hipError_t launch_split_stage(const Consts &c, const StageArgs &s, ns_precision prec, int tile,
                               hipStream_t st)
 {
-    if (prec == NS_FP64) return launch_sp_tile<double, double, double>(tile, c, s, st);
+    if (prec == NS_FP64) {
+        switch (s.mode) {
+        case 0: return launch_sp_tile<double, double, double, 0>(tile, c, s, st);
+        case 1: return launch_sp_tile<double, double, double, 1>(tile, c, s, st);
+        case 2: return launch_sp_tile<double, double, double, 2>(tile, c, s, st);
+        case 3: return launch_sp_tile<double, double, double, 3>(tile, c, s, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     // FP32 storage: stage 1 reads the double state, stage 3 writes it.
-    if (s.mode == 1) return launch_sp_tile<double, float, float>(tile, c, s, st);
-    if (s.mode == 2) return launch_sp_tile<float, float, float>(tile, c, s, st);
-    return launch_sp_tile<float, double, float>(tile, c, s, st);
+    switch (s.mode) {
+    case 1: return launch_sp_tile<double, float, float, 1>(tile, c, s, st);
+    case 2: return launch_sp_tile<float, float, float, 2>(tile, c, s, st);
+    case 3: return launch_sp_tile<float, double, float, 3>(tile, c, s, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace ns
