@@ -152,6 +152,25 @@ ns_status rk3_step(const ns_params *p, ns_algo algo, ns_precision prec,
                    double dt, int32_t nsteps, double *state, void *work,
                    size_t work_bytes, ns_diag *diag_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rk3_step
+ * of the fused class (NS_ALGO_FUSED, either precision, default launch shape
+ * of the calling thread) with its workspace taken from a static device
+ * array of ns_noalloc_scratch_bytes() bytes (64 MiB) that the library holds
+ * on every GPU it runs on until the process ends, instead of a caller
+ * buffer.  Enqueues exactly rk3_step's kernels; results are bit-identical to
+ * rk3_step's.  Allocates nothing.  NS_ERR_WORKSPACE if
+ * ns_workspace_bytes(p, NS_ALGO_FUSED, prec) exceeds that size (grids up to
+ * about 80^3), checked before the device is touched; other errors as
+ * rk3_step.  Every call on a GPU uses that GPU's one array: calls that
+ * overlap on one GPU (different streams or threads) race and must be
+ * serialised by the caller. */
+ns_status rk3_step_noalloc(const ns_params *p, ns_precision prec, double dt, int32_t nsteps,
+                           double *state, ns_diag *diag_dev, void *stream);
+
+/* Size in bytes of the static device workspace of rk3_step_noalloc. */
+size_t ns_noalloc_scratch_bytes(void);
+
 /* Diagnostics of state (device, 5*N doubles) into *out_host, in FP64 with a
  * fixed reduction order (bitwise reproducible).  Waits for stream.  work
  * needs ns_workspace_bytes(p, NS_ALGO_FUSED, NS_FP64) bytes.  Returns

@@ -10,7 +10,8 @@ from ._native import (ALGOS, DIAG_NAMES, EXPORTS, NS_ALGO_FUSED, NS_ALGO_SOME, N
                       NS_ERR_UNSUPPORTED, NS_ERR_WORKSPACE, NS_FP32_STORE, NS_FP64, NS_OK,
                       PRECS, TILES, NativeError, diagnostics, lib, make_params,
                       ns_get_fused_config, ns_get_fused_order, ns_residual, ns_set_fused_config, ns_set_fused_order, ns_stage_stream, ns_state_bytes,
-                      ns_workspace_bytes, rk3_step, status_string, tgv_init)
+                      ns_workspace_bytes, rk3_step, rk3_step_noalloc, ns_noalloc_scratch_bytes,
+                      status_string, tgv_init)
 from ._native import (ns_batch_add, ns_batch_create, ns_batch_destroy, ns_batch_info,  # noqa: F401
                       ns_batch_poll, ns_batch_remove, ns_batch_set_graphs, ns_batch_step)
 from .batch import Batch  # noqa: F401

@@ -69,7 +69,8 @@ class ns_instance(ctypes.Structure):
 
 # Exported C symbols, in header order.
 EXPORTS = ("ns_status_string", "ns_state_bytes", "ns_workspace_bytes",
-           "tgv_init", "ns_residual", "rk3_step", "diagnostics", "ns_stage_stream",
+           "tgv_init", "ns_residual", "rk3_step", "rk3_step_noalloc", "ns_noalloc_scratch_bytes",
+           "diagnostics", "ns_stage_stream",
            "ns_set_fused_config", "ns_get_fused_config", "ns_set_fused_order",
            "ns_get_fused_order",
            "ns_batch_create", "ns_batch_destroy", "ns_batch_add", "ns_batch_remove",
@@ -113,6 +114,10 @@ def lib():
         L.ns_residual.argtypes = [P, ctypes.c_int, vp, vp, vp, sz, vp]
         L.rk3_step.restype = ctypes.c_int
         L.rk3_step.argtypes = [P, ctypes.c_int, ctypes.c_int, d, i32, vp, vp, sz, vp, vp]
+        L.rk3_step_noalloc.restype = ctypes.c_int
+        L.rk3_step_noalloc.argtypes = [P, ctypes.c_int, d, i32, vp, vp, vp]
+        L.ns_noalloc_scratch_bytes.restype = sz
+        L.ns_noalloc_scratch_bytes.argtypes = []
         L.diagnostics.restype = ctypes.c_int
         L.diagnostics.argtypes = [P, vp, ctypes.POINTER(ns_diag), vp, sz, vp]
         L.ns_stage_stream.restype = ctypes.c_int
@@ -234,6 +239,20 @@ def rk3_step(p: ns_params, algo: int, prec: int, dt: float, nsteps: int, state,
     d = _ptr(diag_dev, "rk3_step diag_dev", "float64", 64 * max(int(nsteps), 0))
     _check(lib().rk3_step(ctypes.byref(p), int(algo), int(prec), float(dt), int(nsteps),
                           st, w, work_bytes, d, _stream(stream)), "rk3_step")
+
+
+def rk3_step_noalloc(p: ns_params, prec: int, dt: float, nsteps: int, state, diag_dev=None,
+                     stream=None):
+    """rk3_step of the fused class with the library's static device
+    workspace (for callers that cannot allocate)."""
+    st = _ptr(state, "rk3_step_noalloc state", "float64", ns_state_bytes(p))
+    d = _ptr(diag_dev, "rk3_step_noalloc diag_dev", "float64", 64 * max(int(nsteps), 0))
+    _check(lib().rk3_step_noalloc(ctypes.byref(p), int(prec), float(dt), int(nsteps), st, d,
+                                  _stream(stream)), "rk3_step_noalloc")
+
+
+def ns_noalloc_scratch_bytes() -> int:
+    return int(lib().ns_noalloc_scratch_bytes())
 
 
 def diagnostics(p: ns_params, state, work, work_bytes: int = 0, stream=None) -> dict:

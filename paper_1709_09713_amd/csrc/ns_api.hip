@@ -172,6 +172,8 @@ static ns_status check_params(const ns_params *p)
     return NS_OK;
 }
 
+ns_status validate_params(const ns_params *p) { return check_params(p); }
+
 static bool valid_algo(int a) { return a == NS_ALGO_STORED || a == NS_ALGO_FUSED || a == NS_ALGO_SOME; }
 static bool valid_prec(int q) { return q == NS_FP64 || q == NS_FP32_STORE; }
 

@@ -46,6 +46,10 @@ hipError_t launch_split_stage(const Consts &c, const StageArgs &s, ns_precision 
 // Planes a block marches beyond its chunk (halo and pipeline depth).
 int fused_extra_planes(int tile);
 
+// Argument check of an ns_params (grid range, finite positive lengths and
+// physics); NS_OK, NS_ERR_ARG or NS_ERR_SHAPE.
+ns_status validate_params(const ns_params *p);
+
 // A validated fused-class RK3 plan for one solve: constants, launch shape
 // and the carve-up of its workspace.  rk3_step and the batch scheduler
 // enqueue steps through it, so both run the same launches.

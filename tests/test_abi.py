@@ -297,3 +297,26 @@ def test_launch_settings_are_per_thread():
     assert set(seen["b"]) == {((9, 11), 0)}
     assert ns.ns_get_fused_config(p) == default
     assert ns.ns_get_fused_order() == 0
+
+
+def test_noalloc_validates_before_touching_the_device():
+    """rk3_step_noalloc rejects arguments, and grids whose workspace exceeds
+    its static array, before any device call."""
+    limit = ns.ns_noalloc_scratch_bytes()
+    assert limit == 64 << 20
+    big = ns.make_params(128)
+    assert ns.ns_workspace_bytes(big, ns.NS_ALGO_FUSED, ns.NS_FP64) > limit
+    cases = [
+        (big, ns.NS_FP64, 1e-3, 1, 0x1000, ns.NS_ERR_WORKSPACE),
+        (ns.make_params(4), ns.NS_FP64, 1e-3, 1, 0x1000, ns.NS_ERR_SHAPE),
+        (ns.make_params(16), 7, 1e-3, 1, 0x1000, ns.NS_ERR_ARG),
+        (ns.make_params(16), ns.NS_FP64, 1e-3, 1, 0x1008, ns.NS_ERR_ARG),
+        (ns.make_params(16), ns.NS_FP64, 0.0, 1, 0x1000, ns.NS_ERR_ARG),
+        (ns.make_params(16), ns.NS_FP64, 1e-3, -1, 0x1000, ns.NS_ERR_ARG),
+    ]
+    for p, prec, dt, k, st, code in cases:
+        with pytest.raises(ns.NativeError) as e:
+            ns.rk3_step_noalloc(p, prec, dt, k, st)
+        assert e.value.status == code, (p.n[:], prec, dt, k)
+    # zero steps: nothing to do, nothing touched
+    ns.rk3_step_noalloc(ns.make_params(16), ns.NS_FP64, 1e-3, 0, 0x1000)
