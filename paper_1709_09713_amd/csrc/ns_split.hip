@@ -446,10 +446,6 @@ split_stage_kernel(Consts c, StageArgs s)
         for (int it = 0; it < L; it += 5) chunk(it);
     } else {
         // ------------------------------------------------------------ group E
-        // E's instruction stream is the longer one (measured: E busy ~92%
-        // of the march, M ~75%), so its waves get the higher issue
-        // priority on their SIMD
-        __builtin_amdgcn_s_setprio(2);
         enum { Z_E, Z_U, Z_V, Z_W, Z_RHO, NZ };
         constexpr int R_EN = 0, R_MASS = 1;
         constexpr int NR = 2;
