@@ -297,12 +297,15 @@ split_stage_kernel(Consts c, StageArgs s)
                 for (int f = 0; f < NF; ++f) {
                     if constexpr (PAIR) {
                         // one 2-wide store per field: consecutive lanes
-                        // write consecutive 2-point cells
+                        // write consecutive 2-point cells.  Indexing the
+                        // row as an array of pairs (idx is even, rows start
+                        // 16-byte aligned) lets the compiler use one
+                        // 16-byte LDS store instead of two 8-byte halves.
                         typedef CT pair_t __attribute__((ext_vector_type(2)));
                         pair_t v2;
                         v2.x = val[f][0];
                         v2.y = val[f][1];
-                        *(pair_t *)&lds[b][f][idx] = v2;
+                        ((pair_t *)&lds[b][f][0])[idx >> 1] = v2;
                     } else {
                         lds[b][f][idx] = val[f][0];
                     }
