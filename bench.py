@@ -456,7 +456,7 @@ def serving(tuner, seeds=SERVE_SEEDS, count=SERVE_REQUESTS, rate=50.0):
     first-come-first-served FP64 solves of the same requests.  The offered
     load exceeds what the device sustains, so these latencies are mostly
     queueing; the highest sustained rate is then measured: the server runs
-    fresh streams at 0.75 and 0.9 of the rate its measured capacity predicts,
+    fresh streams at 0.75, 0.9 and 1.0 of the rate its measured capacity predicts,
     and a rate counts as sustained if the backlog at the last arrival stays
     within two batches of members and the last quarter's mean latency within
     twice the first quarter's."""
@@ -494,7 +494,7 @@ def serving(tuner, seeds=SERVE_SEEDS, count=SERVE_REQUESTS, rate=50.0):
     out["capacity_updates_per_s"] = capacity
     out["predicted_sustainable_rate_hz"] = predicted
     runs = []
-    for frac in (0.75, 0.9):
+    for frac in (0.75, 0.9, 1.0):
         r_hz = frac * predicted
         reqs = synth.poisson_requests(100, count, rate_hz=r_hz)
         torch.cuda.synchronize()

@@ -114,7 +114,8 @@ fused_stage_kernel(Consts c, StageArgs s)
     constexpr int NLOAD = (HP + PW * NT - 1) / (PW * NT);
     enum { L_RHO, L_M0, L_M1, L_M2, L_E, L_U, L_V, L_W, L_P, L_T, NF };
     enum { Z_RHO, Z_E, Z_U, Z_V, Z_W, NZ };
-    __shared__ CT lds[2][NF][HP];
+    static_assert(HP % 2 == 0, "pair cells start at even LDS offsets");
+    __shared__ __attribute__((aligned(16))) CT lds[2][NF][HP];
     __shared__ double red[NT / 64 + 1][kDiag];
 
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
@@ -203,13 +204,27 @@ fused_stage_kernel(Consts c, StageArgs s)
     CT qz[5][NZ];                 // ring: (rho, rhoE, u, v, w) of the own column
     CT qa[5], qb[5], qc[5];       // ring: D_x u + D_y v, D_x w, D_y w
     CT ra[5][NR];                 // ring: pending residuals (5) (+ omega_z)
-    TIN pf[NLOAD][5][PW];         // next plane, prefetched
+    // Vector memory counters retire loads and stores in issue order, so a
+    // wait for a load issued after a store also waits for that store.  With
+    // FP32 storage (stages 2 and 3, and the residual) the next plane is
+    // therefore loaded two steps ahead (pg, copied into pf at the end of a
+    // step) and the accumulator of the next step's output point one step
+    // ahead, both before the step's stores.  FP64 storage, whose doubled
+    // prefetch registers cost more than the ordering gains (measured), and
+    // the own-column stage 1 of FP32 storage, short of registers, load one
+    // plane ahead and the accumulator at the start of its step.
+    constexpr bool AHEAD2 = !OWN && std::is_same<TIN, float>::value;
+    TIN pf[NLOAD][5][PW];         // plane zp + 1, staged in step zp
+    TIN pg[AHEAD2 ? NLOAD : 1][5][PW];   // plane zp + 2, loaded in step zp (AHEAD2)
     double accpf[5];              // accumulator (or exact state) of the output point
+    double accn[5];               // the next step's, prefetched (AHEAD2)
     double ocol[3][5];            // exact state of the own column, three planes (OWN only)
 #pragma unroll
     for (int q = 0; q < 3; ++q)
 #pragma unroll
         for (int f = 0; f < 5; ++f) ocol[q][f] = 0.0;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) accpf[f] = accn[f] = 0.0;
     double dsum[DIAG ? 7 : 1];
 #pragma unroll
     for (int k = 0; k < (DIAG ? 7 : 1); ++k) dsum[k] = 0.0;
@@ -222,7 +237,7 @@ fused_stage_kernel(Consts c, StageArgs s)
         for (int f = 0; f < NR; ++f) ra[q][f] = CT(0);
     }
 
-    auto load_plane = [&](int zp) {
+    auto load_plane = [&](int zp, TIN (&dst)[NLOAD][5][PW]) {
         // zp is in [-2, nz + 6] (march padding): at most two wraps
         int zw = zp < 0 ? zp + c.nz : zp;
         zw = zw >= c.nz ? zw - c.nz : zw;
@@ -238,10 +253,10 @@ fused_stage_kernel(Consts c, StageArgs s)
                 if constexpr (PAIR) {
                     typedef TIN pair_t __attribute__((ext_vector_type(2)));
                     const pair_t v = *(const pair_t *)(qin + g + f * N);
-                    pf[r][f][0] = v.x;
-                    pf[r][f][1] = v.y;
+                    dst[r][f][0] = v.x;
+                    dst[r][f][1] = v.y;
                 } else {
-                    pf[r][f][0] = qin[g + f * N];
+                    dst[r][f][0] = qin[g + f * N];
                 }
             }
         }
@@ -249,11 +264,11 @@ fused_stage_kernel(Consts c, StageArgs s)
     // conserved (pf) -> primitives -> LDS buffer b
     auto stage_plane = [&](int b) {
 #pragma unroll
-        for (int r = 0; r < NLOAD; ++r)
+        for (int r = 0; r < NLOAD; ++r) {
+            if (lcell[r] < 0) continue;
+            CT val[NF][PW];
 #pragma unroll
-        for (int j = 0; j < PW; ++j) {
-            const int idx = lcell[r] + j;
-            if (lcell[r] >= 0) {
+            for (int j = 0; j < PW; ++j) {
                 const CT rho = to_ct<TIN, CT>(pf[r][0][j], c.rho_ref);
                 const CT m0 = to_ct<TIN, CT>(pf[r][1][j], 0.0);
                 const CT m1 = to_ct<TIN, CT>(pf[r][2][j], 0.0);
@@ -266,16 +281,30 @@ fused_stage_kernel(Consts c, StageArgs s)
                 // T = gamma M^2 p / rho; as a deviation from T = 1 when the
                 // reference state satisfies gamma M^2 p_ref = rho_ref = 1.
                 const CT T = DEV ? (gM2 * p - rho) * inv : gM2 * p * inv;
-                lds[b][L_RHO][idx] = rho;
-                lds[b][L_M0][idx] = m0;
-                lds[b][L_M1][idx] = m1;
-                lds[b][L_M2][idx] = m2;
-                lds[b][L_E][idx] = E;
-                lds[b][L_U][idx] = u;
-                lds[b][L_V][idx] = v;
-                lds[b][L_W][idx] = w;
-                lds[b][L_P][idx] = p;
-                lds[b][L_T][idx] = T;
+                val[L_RHO][j] = rho;
+                val[L_M0][j] = m0;
+                val[L_M1][j] = m1;
+                val[L_M2][j] = m2;
+                val[L_E][j] = E;
+                val[L_U][j] = u;
+                val[L_V][j] = v;
+                val[L_W][j] = w;
+                val[L_P][j] = p;
+                val[L_T][j] = T;
+            }
+            const int idx = lcell[r];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                if constexpr (PAIR) {
+                    // one 2-wide LDS store per field and pair (idx is even)
+                    typedef CT pair_t __attribute__((ext_vector_type(2)));
+                    pair_t v2;
+                    v2.x = val[f][0];
+                    v2.y = val[f][1];
+                    ((pair_t *)&lds[b][f][0])[idx >> 1] = v2;
+                } else {
+                    lds[b][f][idx] = val[f][0];
+                }
             }
         }
     };
@@ -301,28 +330,34 @@ fused_stage_kernel(Consts c, StageArgs s)
         const int zf = zp - 2;
         const bool fin = active && zf >= z0 && zf < z1;
 
-        // issue the loads of the output point's accumulator and of the next
-        // plane; they complete while this plane is computed.  Loads and
-        // stores retire in issue order, so the accumulator (needed first)
-        // is requested first.
-        {
-            // stages 2 and 3 read the accumulator; the residual and stage 1
-            // read the exact double input state (unused for the residual).
-            // Threads with no output point read a valid address they ignore.
-            if constexpr (OWN) {
-                // stage 1 only: the exact state of plane zp - 2, loaded
-                // three steps ago as this thread's slot 0
+        // issue the loads of the next planes and accumulators (see above);
+        // threads with no output point read a valid address they ignore
+        // stages 2 and 3 read the accumulator; the residual and stage 1
+        // read the exact double input state (unused for the residual)
+        const double *src = (s.mode >= 2) ? s.acc_in : (const double *)s.qin;
+        if constexpr (AHEAD2) {
+            load_plane(zp + 2, pg);
+            const int zn = zf + 1;
+            const int64_t pn = (int64_t)((active && zn >= z0 && zn < z1) ? zn : z0) * c.nxy
+                               + (active ? col : 0);
 #pragma unroll
-                for (int f = 0; f < 5; ++f) accpf[f] = ocol[2][f];
-            } else {
-                const double *src = (s.mode >= 2) ? s.acc_in : (const double *)s.qin;
-                const int zc = fin ? zf : z0;
-                const int64_t pidx = (int64_t)zc * c.nxy + (active ? col : 0);
-#pragma unroll
-                for (int f = 0; f < 5; ++f) accpf[f] = __builtin_nontemporal_load(src + f * N + pidx);
+            for (int f = 0; f < 5; ++f) {
+                accpf[f] = accn[f];
+                accn[f] = __builtin_nontemporal_load(src + f * N + pn);
             }
+        } else if constexpr (OWN) {
+            // stage 1 of FP32 storage: the exact state of plane zp - 2,
+            // loaded three steps ago as this thread's slot 0
+#pragma unroll
+            for (int f = 0; f < 5; ++f) accpf[f] = ocol[2][f];
+            load_plane(zp + 1, pf);
+        } else {
+            // the accumulator, needed first, is requested first
+            const int64_t pidx = (int64_t)(fin ? zf : z0) * c.nxy + (active ? col : 0);
+#pragma unroll
+            for (int f = 0; f < 5; ++f) accpf[f] = __builtin_nontemporal_load(src + f * N + pidx);
+            load_plane(zp + 1, pf);
         }
-        load_plane(zp + 1);
 
         // the slot of plane zp + 2 is free (plane zp - 3 was finished)
 #pragma unroll
@@ -570,13 +605,22 @@ fused_stage_kernel(Consts c, StageArgs s)
         }
 
         if constexpr (OWN) shift_ocol();
+        if constexpr (AHEAD2) {
+#pragma unroll
+            for (int r = 0; r < NLOAD; ++r)
+#pragma unroll
+                for (int f = 0; f < 5; ++f)
+#pragma unroll
+                    for (int j = 0; j < PW; ++j) pf[r][f][j] = pg[r][f][j];
+        }
         lds_barrier();
     };
 
     // prologue: plane z0 - 2 into LDS buffer 0
-    load_plane(z0 - 2);
+    load_plane(z0 - 2, pf);
     stage_plane(0);
     if constexpr (OWN) shift_ocol();
+    if constexpr (AHEAD2) load_plane(z0 - 1, pf);
     lds_barrier();
 
     // The march covers planes z0-2 .. z1+1, padded to a multiple of 5;
