@@ -71,6 +71,44 @@ __device__ __forceinline__ T d2u(T fm2, T fm1, T f0, T fp1, T fp2)
     return T(16) * (fm1 + fp1) - (fm2 + fp2) - T(30) * f0;
 }
 
+// Cross-lane moves of a per-lane value by one lane within the 64-wide wave
+// (DPP wave shifts): lane_prev gives lane i the value of lane i - 1,
+// lane_next that of lane i + 1.  A lane with no source lane (lane 0, resp.
+// lane 63) gets 0.  Every lane of the wave must be active.  Doubles move as
+// two 32-bit halves; the bits are copied exactly.
+__device__ __forceinline__ int dpp_wave_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_wave_shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
+__device__ __forceinline__ float lane_prev(float v) { return __int_as_float(dpp_wave_shr1(__float_as_int(v))); }
+__device__ __forceinline__ float lane_next(float v) { return __int_as_float(dpp_wave_shl1(__float_as_int(v))); }
+__device__ __forceinline__ double lane_prev(double v)
+{
+    return __hiloint2double(dpp_wave_shr1(__double2hiint(v)), dpp_wave_shr1(__double2loint(v)));
+}
+__device__ __forceinline__ double lane_next(double v)
+{
+    return __hiloint2double(dpp_wave_shl1(__double2hiint(v)), dpp_wave_shl1(__double2loint(v)));
+}
+
+// x-derivative (unscaled eq. fd) of a per-column value y that every lane of
+// a tile row holds, for tile rows of BX lanes laid out along the wave (BX
+// divides 64).  The four x-neighbours come from neighbouring lanes; the two
+// lanes at each end of a row take the values they lack from h, which each
+// lane of the row's left half holds for column x - 2 and each lane of the
+// right half for column x + 2.
+template <int BX, typename T>
+__device__ __forceinline__ T d1u_x_lanes(T y, T h, int tx)
+{
+    static_assert(BX >= 4 && 64 % BX == 0, "tile rows must tile the wave, two lanes per end");
+    const T p1 = lane_prev(y), p2 = lane_prev(p1);
+    const T n1 = lane_next(y), n2 = lane_next(n1);
+    const T hn = lane_next(h), hp = lane_prev(h);
+    const T ym2 = tx >= 2 ? p2 : h;             // x - 2
+    const T ym1 = tx >= 1 ? p1 : hn;            // x - 1 (row start: lane 1's x - 2)
+    const T yp1 = tx <= BX - 2 ? n1 : hp;       // x + 1 (row end: lane BX-2's x + 2)
+    const T yp2 = tx <= BX - 3 ? n2 : h;        // x + 2
+    return d1u(ym2, ym1, yp1, yp2);
+}
+
 // XCD-aware tile order.  The dispatcher hands workgroups to the 8 XCDs
 // round-robin by linear workgroup id, and each XCD has its own L2.  Remap so
 // that XCD k processes the k-th contiguous run of tiles (x fastest, then y,

@@ -99,6 +99,11 @@ template <int BX, int BY, typename TIN, typename TOUT, typename CT, int MODE, bo
 __global__ void __launch_bounds__(2 * BX * BY)
 split_stage_kernel(Consts c, StageArgs s)
 {
+    // Multiply-adds are fused only within one expression, never across
+    // statements: the march's five phases are compiled separately, and
+    // fusion across statements can differ between them, which would make a
+    // point's rounding depend on where its plane falls in a z-chunk.
+#pragma clang fp contract(on)
     static_assert(MODE != 1 || std::is_same<TIN, double>::value, "stage 1 reads the double state");
     static_assert(!DIAG || MODE == 1, "diagnostics of the step's input state are taken in stage 1");
     static_assert(BX % 2 == 0, "pairs need an even tile width");
@@ -179,16 +184,6 @@ split_stage_kernel(Consts c, StageArgs s)
 #define DY1H() d1u(HF(-2, 0, L_V), HF(-1, 0, L_V), HF(1, 0, L_V), HF(2, 0, L_V))
 #define DX2(f) d2u(LV(f, 0, -2), LV(f, 0, -1), LV(f, 0, 0), LV(f, 0, 1), LV(f, 0, 2))
 #define DY2(f) d2u(LV(f, -2, 0), LV(f, -1, 0), LV(f, 0, 0), LV(f, 1, 0), LV(f, 2, 0))
-#define DXDY(f)                                                          \
-    d1u(d1u(LV(f, -2, -2), LV(f, -1, -2), LV(f, 1, -2), LV(f, 2, -2)),   \
-        d1u(LV(f, -2, -1), LV(f, -1, -1), LV(f, 1, -1), LV(f, 2, -1)),   \
-        d1u(LV(f, -2, 1), LV(f, -1, 1), LV(f, 1, 1), LV(f, 2, 1)),       \
-        d1u(LV(f, -2, 2), LV(f, -1, 2), LV(f, 1, 2), LV(f, 2, 2)))
-#define DYDX(f)                                                          \
-    d1u(d1u(LV(f, -2, -2), LV(f, -2, -1), LV(f, -2, 1), LV(f, -2, 2)),   \
-        d1u(LV(f, -1, -2), LV(f, -1, -1), LV(f, -1, 1), LV(f, -1, 2)),   \
-        d1u(LV(f, 1, -2), LV(f, 1, -1), LV(f, 1, 1), LV(f, 1, 2)),       \
-        d1u(LV(f, 2, -2), LV(f, 2, -1), LV(f, 2, 1), LV(f, 2, 2)))
 
     if (!grp_e) {
         // ------------------------------------------------------------ group M
@@ -493,8 +488,9 @@ split_stage_kernel(Consts c, StageArgs s)
                 const CT E = LV(L_E, 0, 0), rho = LV(L_RHO, 0, 0);
                 const CT u = LV(L_U, 0, 0), v = LV(L_V, 0, 0), w = LV(L_W, 0, 0);
                 const CT p = LV(L_P, 0, 0), T = LV(L_T, 0, 0), m2 = LV(L_M2, 0, 0);
-                const CT Gxx = c1x * DX1(L_U), Gxy = c1y * DY1(L_U);
-                const CT Gyx = c1x * DX1(L_V), Gyy = c1y * DY1(L_V);
+                const CT dyu = DY1(L_U), dyv = DY1(L_V);
+                const CT Gxx = c1x * DX1(L_U), Gxy = c1y * dyu;
+                const CT Gyx = c1x * DX1(L_V), Gyy = c1y * dyv;
                 const CT Gzx = c1x * DX1(L_W), Gzy = c1y * DY1(L_W);
                 const CT a = Gxx + Gyy;
                 qz[S0][Z_E] = E;
@@ -525,11 +521,23 @@ split_stage_kernel(Consts c, StageArgs s)
 
                 if (do_plane) {
                     const CT uc = u * c1x, vc = v * c1y;
+                    // mixed derivatives d_x d_y v and d_x d_y u: the x-stencil
+                    // applied across the row's lanes to the y-derivatives
+                    // they already hold; a row's two end lanes on each side
+                    // take the y-derivative at their halo column (x - 2 in
+                    // the left half of the row, x + 2 in the right half)
+                    const int hx = (tx < BX / 2) ? -2 : 2;
+#define LVH(f, dy) lds[b][f][own + (dy) * HX + hx]
+                    const CT hu = d1u(LVH(L_U, -2), LVH(L_U, -1), LVH(L_U, 1), LVH(L_U, 2));
+                    const CT hv = d1u(LVH(L_V, -2), LVH(L_V, -1), LVH(L_V, 1), LVH(L_V, 2));
+#undef LVH
+                    const CT dxdyv = d1u_x_lanes<BX>(dyv, hv, tx);
+                    const CT dxdyu = d1u_x_lanes<BX>(dyu, hu, tx);
                     // d_j tau_ij = lap u_i + (1/3) d_i div u, in-plane parts
                     const CT Vx = four3 * (c2x * DX2(L_U)) + c2y * DY2(L_U)
-                                  + third * (c1x * c1y * DXDY(L_V));
+                                  + third * (c1x * c1y * dxdyv);
                     const CT Vy = c2x * DX2(L_V) + four3 * (c2y * DY2(L_V))
-                                  + third * (c1x * c1y * DYDX(L_U));
+                                  + third * (c1x * c1y * dxdyu);
                     const CT Vz = c2x * DX2(L_W) + c2y * DY2(L_W);
                     vbuf[b][0][pt] = Vx;
                     vbuf[b][1][pt] = Vy;
@@ -635,8 +643,6 @@ split_stage_kernel(Consts c, StageArgs s)
 #undef DY1H
 #undef DX2
 #undef DY2
-#undef DXDY
-#undef DYDX
 
     if constexpr (DIAG) {
         // block reduction of the diagnostic partial sums, fixed order: each
