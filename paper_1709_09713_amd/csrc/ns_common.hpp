@@ -92,9 +92,9 @@ __device__ __forceinline__ double lane_next(double v)
 // x-derivative (unscaled eq. fd) of a per-column value y that every lane of
 // a tile row holds, for tile rows of BX lanes laid out along the wave (BX
 // divides 64).  The four x-neighbours come from neighbouring lanes; the two
-// lanes at each end of a row take the values they lack from h, which each
-// lane of the row's left half holds for column x - 2 and each lane of the
-// right half for column x + 2.
+// lanes at each end of a row take the values they lack from h, which the
+// first two lanes of a row (tx 0, 1) hold for column x - 2 and the last two
+// (tx BX-2, BX-1) for column x + 2.  The other lanes' h is not used.
 template <int BX, typename T>
 __device__ __forceinline__ T d1u_x_lanes(T y, T h, int tx)
 {

@@ -524,9 +524,11 @@ split_stage_kernel(Consts c, StageArgs s)
                     // mixed derivatives d_x d_y v and d_x d_y u: the x-stencil
                     // applied across the row's lanes to the y-derivatives
                     // they already hold; a row's two end lanes on each side
-                    // take the y-derivative at their halo column (x - 2 in
-                    // the left half of the row, x + 2 in the right half)
-                    const int hx = (tx < BX / 2) ? -2 : 2;
+                    // take the y-derivative at their halo column (x - 2 at
+                    // the start of the row, x + 2 at its end).  The other
+                    // lanes read their own column, which keeps the wave's
+                    // addresses on distinct LDS banks.
+                    const int hx = (tx < 2) ? -2 : (tx >= BX - 2 ? 2 : 0);
 #define LVH(f, dy) lds[b][f][own + (dy) * HX + hx]
                     const CT hu = d1u(LVH(L_U, -2), LVH(L_U, -1), LVH(L_U, 1), LVH(L_U, 2));
                     const CT hv = d1u(LVH(L_V, -2), LVH(L_V, -1), LVH(L_V, 1), LVH(L_V, 2));
