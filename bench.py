@@ -177,7 +177,9 @@ def cpu_baseline(n):
     TGV on all threads and the residual at 2^20 sampled points of it on one
     thread, and one RK3 step per grid size of the batched / serving mixes,
     from which the oracle's time for the 64-instance batch (seed 0) and for
-    a stratified 16-request sample of the serving stream is projected."""
+    a stratified sample of at least 16 requests of the serving stream is
+    projected.  The recorded times of the full 256^3 x 100 and 512^3 x 50
+    oracle runs behind the stored samples are added as found."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     out = {"unit": "updates/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model()}
@@ -251,6 +253,17 @@ def cpu_baseline(n):
         "updates_per_s": sum(r["n"] ** 3 * 3 * r["steps"] for r in sample) / sum(solve),
         "method": "up to 3 requests of each grid size from the seed-0 stream, each request's "
                   "solve time at the measured rate of its grid size"}
+    # the full 256^3 x 100 and 512^3 x 50 oracle runs, made once by
+    # tests/golden/make_tgv_oracle_samples.py on the machine that wrote the
+    # stored samples (not this host): their recorded time and thread count
+    full = {}
+    for fn, fs in ((256, 100), (512, 50)):
+        z = golden(fn, fs)
+        if z is not None:
+            sec = float(z["oracle_seconds"])
+            full[f"tgv{fn}_{fs}steps"] = {"seconds": sec, "threads": int(z["oracle_threads"]),
+                                          "updates_per_s": fn ** 3 * 3 * fs / sec}
+    out["full_runs_of_stored_samples"] = full
     out["paper_context_24core_ivy_bridge"] = {"BL": 2.07e7, "SN": 4.58e7}
     log(f"bench cpu: baseline {out['value']:.3e} updates/s on {threads} threads")
     return out
