@@ -119,12 +119,6 @@ split_stage_kernel(Consts c, StageArgs s)
     // E -> M: (V_x, V_y, V_z) in-plane part at plane zp, z part at plane zp - 2
     __shared__ CT vbuf[2][6][NT];
     __shared__ double red[NW][kDiag];
-    // per-column diagnostic sums (stage 1 with diagnostics): each thread adds
-    // into its own slots with no-return LDS adds, so the sums cost no
-    // registers and no waits during the march.  Slots: 0 mass, 4 energy,
-    // 5 kinetic energy and 6 enstrophy (E), 1-3 momentum (M)
-    constexpr int ND = DIAG ? 7 : 1;
-    __shared__ double dacc[ND][NT];
 
     // The group is a property of the wave; reading it through a scalar
     // register makes the branch below a scalar branch, so each wave runs
@@ -152,18 +146,10 @@ split_stage_kernel(Consts c, StageArgs s)
     const CT two3 = CT(2) / CT(3);
     const CT kz = kappa * c2z;
 
-    if constexpr (DIAG) {
-        if (!grp_e) {
-#pragma unroll
-            for (int k = 1; k < 4; ++k) dacc[k][pt] = 0.0;
-        } else {
-            dacc[0][pt] = dacc[4][pt] = dacc[5][pt] = dacc[6][pt] = 0.0;
-        }
-    }
-    // in-order adds to a thread's own slot: deterministic sums
-    auto dadd = [&](int k, double v) {
-        __hip_atomic_fetch_add(&dacc[k][pt], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    };
+    // per-column diagnostic sums of stage 1 with diagnostics, added in
+    // program order (deterministic): group M the three momenta, group E mass,
+    // energy, kinetic energy and enstrophy
+    double dr[4] = {0.0, 0.0, 0.0, 0.0};
 
     // The march covers planes z0-2 .. z1+2 (M finishes a plane three steps
     // after loading it), padded to a multiple of 5; padding planes are
@@ -397,7 +383,7 @@ split_stage_kernel(Consts c, StageArgs s)
                     } else {
                         if constexpr (DIAG) {
 #pragma unroll
-                            for (int f = 0; f < 3; ++f) dadd(1 + f, acc[f]);
+                            for (int f = 0; f < 3; ++f) dr[f] += acc[f];
                         }
 #pragma unroll
                         for (int f = 0; f < 3; ++f) {
@@ -558,9 +544,9 @@ split_stage_kernel(Consts c, StageArgs s)
                         const double oz = (double)(Gyx - Gxy);
                         const double rd = (double)rhof;
                         if (active) {
-                            dadd(5, 0.5 * rd * ((double)u * (double)u + (double)v * (double)v
-                                                + (double)w * (double)w));
-                            dadd(6, 0.5 * rd * oz * oz);
+                            dr[2] += 0.5 * rd * ((double)u * (double)u + (double)v * (double)v
+                                                + (double)w * (double)w);
+                            dr[3] += 0.5 * rd * oz * oz;
                         }
                     }
                     ra[S0][R_EN] += -(c1x * DX1H() + c1y * DY1H())
@@ -605,9 +591,9 @@ split_stage_kernel(Consts c, StageArgs s)
                     } else {
                         if constexpr (DIAG) {
                             const CT ox = cc - Gyz, oy = Gxz - bb;
-                            dadd(0, acc0);
-                            dadd(4, acc4);
-                            dadd(6, 0.5 * (double)rhof * ((double)ox * (double)ox + (double)oy * (double)oy));
+                            dr[0] += acc0;
+                            dr[1] += acc4;
+                            dr[3] += 0.5 * (double)rhof * ((double)ox * (double)ox + (double)oy * (double)oy);
                         }
                         sp_store<TOUT>(s.qout, pidx, acc0 + s.a_dt * Rd0, c.rho_ref);
                         sp_store<TOUT>(s.qout, 4 * N + pidx, acc4 + s.a_dt * Rd4, c.rhoE_ref);
@@ -652,11 +638,16 @@ split_stage_kernel(Consts c, StageArgs s)
         // group's slots count zero for it), then waves, then the block
         const int tid = threadIdx.x;
         __syncthreads();
-        double dsum[7];
-#pragma unroll
-        for (int k = 0; k < 7; ++k) {
-            const bool mine = grp_e ? (k == 0 || k >= 4) : (k >= 1 && k <= 3);
-            dsum[k] = mine ? dacc[k][pt] : 0.0;
+        double dsum[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (grp_e) {
+            dsum[0] = dr[0];
+            dsum[4] = dr[1];
+            dsum[5] = dr[2];
+            dsum[6] = dr[3];
+        } else {
+            dsum[1] = dr[0];
+            dsum[2] = dr[1];
+            dsum[3] = dr[2];
         }
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
