@@ -25,7 +25,10 @@
 // five-deep ring of pending residuals, point-value-weighted terms gathered
 // from a ring of primitives, mixed derivatives as z derivatives of in-plane
 // ones), the FP32 deviation storage format and the diagnostics of the stage
-// input follow the one-thread kernel.
+// input follow the one-thread kernel.  The in-plane mixed derivatives
+// d_x d_y u and d_x d_y v differ: group E applies the x-stencil across the
+// lanes of a tile row to the y-derivatives the lanes already hold (DPP wave
+// shifts), where the one-thread kernel reads 16 LDS taps.
 #include <type_traits>
 
 #include "ns_common.hpp"
