@@ -185,9 +185,13 @@ ns_status diagnostics(const ns_params *p, const double *state,
  * both, stage 3 reads both and writes state, the same buffers rk3_step uses
  * in work -- with a pointwise update instead of the residual.  Its rate is
  * the ceiling that the memory system allows the fused stage kernel's access
- * pattern.  work needs ns_workspace_bytes(p, NS_ALGO_FUSED, NS_FP64) bytes;
- * state and the workspace buffers are overwritten with meaningless values.
- * NS_ERR_ARG for stage outside 1..3. */
+ * pattern.  work needs ns_workspace_bytes(p, NS_ALGO_FUSED, NS_FP64) bytes.
+ * The update of every element, with a = 1/2, b = 1/4: stage 1 sets the
+ * stage buffer to Q + a Q and the accumulator to Q + b Q; stage 2 sets the
+ * second stage buffer to acc + a s1 and acc to acc + b s1; stage 3 sets
+ * state to acc + a s2.  Stages 1, 2, 3 in a row thus leave 2.625 Q in state
+ * (exact when the products and sums are).  NS_ERR_ARG for stage outside
+ * 1..3. */
 ns_status ns_stage_stream(const ns_params *p, int32_t stage, double *state, void *work,
                           size_t work_bytes, void *stream);
 

@@ -26,12 +26,15 @@ typedef double d2_t __attribute__((ext_vector_type(2)));
 // the stores); 64 blocks of 256 lanes per compute unit keep enough bytes in
 // flight (the fastest of the shapes measured: 8-64 blocks per CU, one to
 // four chunks per lane, non-temporal or cached accesses, 4.7-5.2 TB/s).
+// An odd count leaves one double after the last pair; the first lane of
+// block 0 moves it.
 template <int MODE>
-__global__ void __launch_bounds__(256) stream_stage_kernel(int64_t npairs, const d2_t *__restrict__ qin,
+__global__ void __launch_bounds__(256) stream_stage_kernel(int64_t n5, const d2_t *__restrict__ qin,
                                                            const d2_t *__restrict__ acc_in,
                                                            d2_t *__restrict__ acc_out,
                                                            d2_t *__restrict__ qout, double a, double b)
 {
+    const int64_t npairs = n5 / 2;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i + stride < npairs; i += 2 * stride) {
@@ -50,6 +53,13 @@ __global__ void __launch_bounds__(256) stream_stage_kernel(int64_t npairs, const
         const d2_t acc = (MODE == 1) ? q : __builtin_nontemporal_load(acc_in + i);
         __builtin_nontemporal_store(acc + a * q, qout + i);
         if (MODE != 3) __builtin_nontemporal_store(acc + b * q, acc_out + i);
+    }
+    if ((n5 & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t k = n5 - 1;
+        const double q = ((const double *)qin)[k];
+        const double acc = (MODE == 1) ? q : ((const double *)acc_in)[k];
+        ((double *)qout)[k] = acc + a * q;
+        if (MODE != 3) ((double *)acc_out)[k] = acc + b * q;
     }
 }
 
@@ -72,9 +82,9 @@ hipError_t launch_stream_stage(int stage, int64_t n5, const double *qin, const d
     d2_t *ao = (d2_t *)acc_out;
     d2_t *qo = (d2_t *)qout;
     switch (stage) {
-    case 1: hipLaunchKernelGGL(stream_stage_kernel<1>, dim3(blocks), dim3(256), 0, st, npairs, q, ai, ao, qo, 0.5, 0.25); break;
-    case 2: hipLaunchKernelGGL(stream_stage_kernel<2>, dim3(blocks), dim3(256), 0, st, npairs, q, ai, ao, qo, 0.5, 0.25); break;
-    case 3: hipLaunchKernelGGL(stream_stage_kernel<3>, dim3(blocks), dim3(256), 0, st, npairs, q, ai, ao, qo, 0.5, 0.25); break;
+    case 1: hipLaunchKernelGGL(stream_stage_kernel<1>, dim3(blocks), dim3(256), 0, st, n5, q, ai, ao, qo, 0.5, 0.25); break;
+    case 2: hipLaunchKernelGGL(stream_stage_kernel<2>, dim3(blocks), dim3(256), 0, st, n5, q, ai, ao, qo, 0.5, 0.25); break;
+    case 3: hipLaunchKernelGGL(stream_stage_kernel<3>, dim3(blocks), dim3(256), 0, st, n5, q, ai, ao, qo, 0.5, 0.25); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
