@@ -76,8 +76,8 @@ __device__ __forceinline__ T d2u(T fm2, T fm1, T f0, T fp1, T fp2)
 // lane_next that of lane i + 1.  A lane with no source lane (lane 0, resp.
 // lane 63) gets 0.  Every lane of the wave must be active.  Doubles move as
 // two 32-bit halves; the bits are copied exactly.
-__device__ __forceinline__ int dpp_wave_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
-__device__ __forceinline__ int dpp_wave_shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_wave_shr1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_wave_shl1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true); }
 __device__ __forceinline__ float lane_prev(float v) { return __int_as_float(dpp_wave_shr1(__float_as_int(v))); }
 __device__ __forceinline__ float lane_next(float v) { return __int_as_float(dpp_wave_shl1(__float_as_int(v))); }
 __device__ __forceinline__ double lane_prev(double v)
