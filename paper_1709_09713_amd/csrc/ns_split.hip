@@ -537,8 +537,16 @@ split_stage_kernel(Consts c, StageArgs s)
                     const CT phi = CT(2) * (Gxx * Gxx + Gyy * Gyy) + Gxy * Gxy + Gyx * Gyx
                                    + CT(2) * Gxy * Gyx + Gzx * Gzx + Gzy * Gzy;
                     const CT rhof = DEV ? CT(1) + rho : rho;
-                    ra[S0][R_MASS] -= half * (c1x * DX1(L_M0) + c1y * DY1(L_M1) + rhof * a
-                                              + uc * DX1(L_RHO) + vc * DY1(L_RHO));
+                    if constexpr (DEV) {
+                        ra[S0][R_MASS] -= half * (c1x * DX1(L_M0) + c1y * DY1(L_M1) + rhof * a
+                                                  + uc * DX1(L_RHO) + vc * DY1(L_RHO));
+                    } else {
+                        // rho u and rho v at the taps, from the rho and
+                        // velocity taps this group reads anyway (equal to
+                        // the staged momenta up to rounding)
+                        ra[S0][R_MASS] -= half * (c1x * DX1P(L_RHO, L_U) + c1y * DY1P(L_RHO, L_V)
+                                                  + rhof * a + uc * DX1(L_RHO) + vc * DY1(L_RHO));
+                    }
                     if constexpr (DIAG) {
                         // the kinetic energy and the omega_z part of the
                         // enstrophy are complete in the plane; the vorticity
