@@ -201,8 +201,8 @@ ns_status ns_stage_stream(const ns_params *p, int32_t stage, double *state, void
  * (x, y) column tile of one block: 0 = 32x8, 1 = 16x16, 2 = 64x4,
  * 3 = 32x16, 4 = 16x8, 5 = 32x4, 6 = 16x4, 7 = 8x8 (threads = product, one
  * z column each); 8 = 16x8, 9 = 32x8, 10 = 16x4 with two threads per
- * column (one evaluates the mass and momentum equations, the other the
- * energy equation and the viscous terms); zchunk is the number of
+ * column (one loads the planes and evaluates the momentum equations, the
+ * other the mass and energy equations and the viscous terms); zchunk is the number of
  * z planes one block marches through (>= 1; 0 = automatic: the length that
  * minimises (rounds of device-resident blocks) x (planes each block
  * marches, chunk + 4 halo planes; + 5 for tiles 8-10)).  tile = -1

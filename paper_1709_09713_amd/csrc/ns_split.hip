@@ -7,10 +7,10 @@
 // z, the low-storage RK3 update of the generic-algorithm figure in the same
 // pass), but a block holds two threads per column of its tile:
 //  * group M (threads [0, NT)) loads and stages each plane into LDS and
-//    evaluates the mass and momentum equations;
-//  * group E (threads [NT, 2 NT)) evaluates the energy equation and the
-//    viscous vector V_i = lap u_i + (1/3) d_i div u, which the momentum
-//    equations need too.  E hands V to M through a small LDS buffer: in the
+//    evaluates the three momentum equations;
+//  * group E (threads [NT, 2 NT)) evaluates the mass and energy equations
+//    and the viscous vector V_i = lap u_i + (1/3) d_i div u, which the
+//    momentum equations need too.  E hands V to M through a small LDS buffer: in the
 //    step of plane zp it writes the in-plane part of V at plane zp and the
 //    z part at plane zp - 2, and M reads both one step later, after the
 //    plane barrier.  So M finishes plane zp - 3 in that step, one plane
