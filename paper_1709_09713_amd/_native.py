@@ -35,7 +35,7 @@ ALGOS = {"stored": NS_ALGO_STORED, "fused": NS_ALGO_FUSED, "some": NS_ALGO_SOME}
 PRECS = {"fp64": NS_FP64, "fp32": NS_FP32_STORE}
 
 # tile code -> (BX, BY) column tile of one block; codes 8-10 run two threads
-# per column (mass/momentum and energy split between two wave groups)
+# per column (momentum in one wave group; mass, energy and the viscous terms in the other)
 TILES = {0: (32, 8), 1: (16, 16), 2: (64, 4), 3: (32, 16), 4: (16, 8), 5: (32, 4),
          6: (16, 4), 7: (8, 8), 8: (16, 8), 9: (32, 8), 10: (16, 4)}
 

@@ -7,8 +7,9 @@ namespace ns {
 
 // Column-tile shapes of the fused kernel.  Tiles 0-7: threads = BX * BY,
 // one z column each (ns_fused.hip).  Tiles 8-10 (_2G): 2 * BX * BY
-// threads, two per column, the mass/momentum and the energy equations
-// split between two wave groups (ns_split.hip).  Chosen per problem by the
+// threads, two per column: the momentum equations in one wave group, the
+// mass and energy equations and the viscous terms in the other
+// (ns_split.hip).  Chosen per problem by the
 // autotuner or by the default rule.
 enum {
     TILE_32x8 = 0, TILE_16x16 = 1, TILE_64x4 = 2, TILE_32x16 = 3,
