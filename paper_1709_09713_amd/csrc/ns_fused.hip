@@ -106,6 +106,10 @@ template <int BX, int BY, typename TIN, typename TOUT, typename CT, bool DIAG, i
 __global__ void __launch_bounds__(BX * BY)
 fused_stage_kernel(Consts c, StageArgs s)
 {
+    // Multiply-adds are fused only within one expression: the five unrolled
+    // phases of the march then round alike, so a point's result does not
+    // depend on where its plane falls in a z-chunk.
+#pragma clang fp contract(on)
     constexpr bool DEV = std::is_same<CT, float>::value;
     static_assert(BX % 2 == 0, "pairs need an even tile width");
     static_assert(!(PAIR && DEV && std::is_same<TIN, double>::value), "own-column loads are single");
